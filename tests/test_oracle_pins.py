@@ -1,0 +1,333 @@
+"""Pins for the CPU oracle: each test checks it against something other than itself.
+
+Hand-worked values, closed forms, invariants, library routines (bincount,
+partition) and brute force on tiny inputs.  Each test names the step of the
+method it pins (Section III-A / III-B of the paper) and the mistake it would
+catch.  None of these tests need a GPU.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def _rgb(pixels):
+    """(H, W, 3) uint8 image from nested lists of (R, G, B)."""
+    return np.array(pixels, dtype=np.uint8)
+
+
+# ---------------------------------------------------------------- gray (Section III-A)
+
+def test_gray_hand_values():
+    # Ward's weights 54/183/19 out of 256, worked by hand:
+    # 54*255/256 = 53.79 -> 53, 183*255/256 = 182.29 -> 182, 19*255/256 = 18.93 -> 18.
+    # A channel-order or weight mistake changes at least one of these.
+    img = _rgb([[(255, 0, 0), (0, 255, 0), (0, 0, 255), (255, 255, 255), (0, 0, 0)]])
+    assert oracle.gray(img).tolist() == [[53, 182, 18, 255, 0]]
+    # (10, 20, 30): 540 + 3660 + 570 = 4770; 4770 / 256 = 18.63 -> 18.
+    assert oracle.gray(_rgb([[(10, 20, 30)]])).tolist() == [[18]]
+
+
+def test_gray_of_gray_is_identity():
+    # The weights sum to 256, so a neutral pixel keeps its value (a wrong shift or sum breaks it).
+    v = np.arange(256, dtype=np.uint8)
+    img = np.stack([v, v, v], axis=-1)[None]
+    assert oracle.gray(img)[0].tolist() == list(range(256))
+
+
+def test_gray_all_triples_exhaustive():
+    # All 2^24 (R, G, B) triples against the floor of the weighted mean.
+    r, g, b = np.meshgrid(np.arange(256), np.arange(256), np.arange(256), indexing="ij")
+    img = np.stack([r, g, b], axis=-1).astype(np.uint8).reshape(4096, 4096, 3)
+    want = ((54 * r.astype(np.int64) + 183 * g + 19 * b) // 256).reshape(4096, 4096)
+    assert np.array_equal(oracle.gray(img), want.astype(np.uint8))
+
+
+def test_gray_monotone_in_each_channel():
+    rng = np.random.default_rng(0)
+    img = rng.integers(0, 255, (64, 64, 3), dtype=np.uint8)
+    base = oracle.gray(img).astype(int)
+    for c in range(3):
+        up = img.copy()
+        up[:, :, c] += 1
+        assert (oracle.gray(up).astype(int) >= base).all()
+
+
+def test_gray_honours_row_stride():
+    rng = np.random.default_rng(1)
+    img = rng.integers(0, 256, (7, 5, 3), dtype=np.uint8)
+    padded = rng.integers(0, 256, (7, 5 * 3 + 13), dtype=np.uint8)
+    padded[:, :15] = img.reshape(7, 15)
+    view = padded[:, :15].reshape(7, 5, 3)  # strided view: rows 28 bytes apart
+    assert view.strides[0] == 28
+    assert np.array_equal(oracle.gray(view), oracle.gray(img))
+
+
+# ---------------------------------------------------------------- pyramid (Section III-A, Fig. 2)
+
+def test_downsample_hand_example():
+    g = np.arange(16, dtype=np.uint8).reshape(4, 4)
+    # Block sums 10, 18, 42, 50 -> floor means 2, 4, 10, 12.
+    assert oracle.downsample(g).tolist() == [[2, 4], [10, 12]]
+
+
+def test_downsample_floors_not_rounds():
+    # (1+2+2+2)/4 = 1.75: floor 1 (rounding would give 2).
+    assert oracle.downsample(np.array([[1, 2], [2, 2]], np.uint8)).tolist() == [[1]]
+    assert oracle.downsample(np.array([[255, 255], [255, 254]], np.uint8)).tolist() == [[254]]
+
+
+def test_downsample_drops_odd_edge():
+    rng = np.random.default_rng(2)
+    g = rng.integers(0, 256, (9, 11), dtype=np.uint8)
+    d = oracle.downsample(g)
+    assert d.shape == (4, 5)
+    g2 = g.copy()
+    g2[8, :] = rng.integers(0, 256, 11)
+    g2[:, 10] = rng.integers(0, 256, 9)
+    assert np.array_equal(oracle.downsample(g2), d)
+
+
+def test_pyramid_is_recursive_not_block_mean():
+    # Three 2x2 blocks summing to 7 and one to 11 give level 1 = [[1,1],[1,2]] and level 2 =
+    # (1+1+1+2)>>2 = 1, while the floor mean of the 16 pixels is 32/16 = 2.
+    a = np.array([[1, 2], [2, 2]])
+    b = np.array([[2, 3], [3, 3]])
+    g = np.block([[a, a], [a, b]]).astype(np.uint8)
+    img = np.stack([g, g, g], axis=-1)
+    p = oracle.pyramid(img, 3)
+    assert p.gray(1).tolist() == [[1, 1], [1, 2]]
+    assert p.gray(2).tolist() == [[1]]
+
+
+def test_pyramid_dims_and_constant_image():
+    img = np.full((37, 53, 3), 77, np.uint8)
+    L = oracle.max_levels(53, 37)
+    assert L == 6  # 37 >> 5 = 1, 37 >> 6 = 0
+    p = oracle.pyramid(img, L)
+    for l in range(L):
+        assert p.gray(l).shape == (37 >> l, 53 >> l)
+        assert (p.gray(l) == 77).all()
+        assert p.median[l] == 77
+        assert p.hist[l][77] == (37 >> l) * (53 >> l)
+
+
+# ---------------------------------------------------------------- histogram and median (Section III-B)
+
+def test_histogram_matches_bincount():
+    rng = np.random.default_rng(3)
+    g = rng.integers(0, 256, (123, 77), dtype=np.uint8)
+    h = oracle.histogram(g)
+    assert np.array_equal(h, np.bincount(g.ravel(), minlength=256))
+    assert h.sum() == g.size
+
+
+def test_median_hand_examples():
+    def med(vals):
+        g = np.array(vals, np.uint8)
+        return oracle.median(oracle.histogram(g), g.size)
+
+    assert med([1, 2, 3, 4]) == 2       # lower median of an even count
+    assert med([5]) == 5
+    assert med([0, 255]) == 0
+    assert med([3, 3, 3]) == 3
+    assert med([9, 1, 5]) == 5
+    assert med([200, 10, 10, 200, 200]) == 200
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 255, 256, 1000, 4097])
+def test_median_is_lower_order_statistic(n):
+    rng = np.random.default_rng(n)
+    g = rng.integers(0, 256, n, dtype=np.uint8)
+    k = (n - 1) // 2
+    assert oracle.median(oracle.histogram(g), n) == int(np.partition(g, k)[k])
+
+
+# ---------------------------------------------------------------- bitmaps (Sections III-A, III-B)
+
+def test_bitmap_threshold_and_exclusion_boundaries():
+    m = 100
+    g = np.arange(m - 6, m + 7, dtype=np.uint8)  # 94 .. 106
+    t, e = oracle.bitmaps(g, m, 4)
+    # Threshold: at or below the median -> 0.
+    assert t.tolist() == [0] * 7 + [1] * 6
+    # Exclusion: values within +-4 of the median (96..104) are excluded, m+-5 kept.
+    assert e.tolist() == [1, 1] + [0] * 9 + [1, 1]
+
+
+def test_threshold_popcount_at_most_half():
+    rng = np.random.default_rng(4)
+    for n in (1, 2, 7, 64, 1001):
+        g = rng.integers(0, 256, n, dtype=np.uint8)
+        if n % 2:
+            g[: n // 2] = 17  # ties at the median
+        m = oracle.median(oracle.histogram(g), n)
+        t, e = oracle.bitmaps(g, m, 4)
+        assert int(t.sum()) <= n // 2
+        assert np.array_equal(e == 0, np.abs(g.astype(int) - m) <= 4)
+
+
+# ---------------------------------------------------------------- shifted error (Sections III-A, III-B)
+
+def _shifted(b, cx, cy):
+    """Zero-filled shift by padded slicing: out[y][x] = b[y - cy][x - cx]."""
+    h, w = b.shape
+    pad = np.zeros((h + 2 * abs(cy) + 2 * h, w + 2 * abs(cx) + 2 * w), b.dtype)
+    oy, ox = abs(cy) + h, abs(cx) + w
+    pad[oy:oy + h, ox:ox + w] = b
+    return pad[oy - cy:oy - cy + h, ox - cx:ox - cx + w]
+
+
+def _brute_error(tr, er, tm, em, cx, cy):
+    return int(((tr ^ _shifted(tm, cx, cy)) & er & _shifted(em, cx, cy)).sum())
+
+
+def test_shift_error_hand_example():
+    # Reference T = 1 everywhere, E = 1 everywhere; moving T = 0, E = 1 on a 3x3 grid.
+    one = np.ones((3, 3), np.uint8)
+    zero = np.zeros((3, 3), np.uint8)
+    assert oracle.shift_error(one, one, zero, one, 0, 0) == 9
+    # Shifted by (1, 0): column 0 is filled with zeros (E = 0), 6 pixels remain.
+    assert oracle.shift_error(one, one, zero, one, 1, 0) == 6
+    # Shifted by (-1, -2): overlap is 2 columns x 1 row.
+    assert oracle.shift_error(one, one, zero, one, -1, -2) == 2
+    # Fully shifted out.
+    assert oracle.shift_error(one, one, zero, one, 3, 0) == 0
+
+
+def test_shift_error_brute_force_all_shifts():
+    rng = np.random.default_rng(5)
+    for h, w in ((5, 7), (8, 8), (13, 6), (1, 9)):
+        tr, er, tm, em = (rng.integers(0, 2, (h, w), dtype=np.uint8) for _ in range(4))
+        for cx in range(-w - 1, w + 2):
+            for cy in range(-h - 1, h + 2):
+                assert oracle.shift_error(tr, er, tm, em, cx, cy) == _brute_error(tr, er, tm, em, cx, cy)
+
+
+def test_shift_error_symmetry_and_self():
+    rng = np.random.default_rng(6)
+    ta, ea, tb, eb = (rng.integers(0, 2, (11, 9), dtype=np.uint8) for _ in range(4))
+    for cx, cy in itertools.product(range(-4, 5), range(-4, 5)):
+        assert oracle.shift_error(ta, ea, tb, eb, cx, cy) == oracle.shift_error(tb, eb, ta, ea, -cx, -cy)
+    assert oracle.shift_error(ta, ea, ta, ea, 0, 0) == 0
+
+
+# ---------------------------------------------------------------- coarse-to-fine search (Section III-A)
+
+def _first_min(surface):
+    """Argmin of a 3x3 surface indexed [dy+1][dx+1], lowest (dy, dx) first."""
+    best = None
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            v = surface[dy + 1][dx + 1]
+            if best is None or v < best[0]:
+                best = (v, dx, dy)
+    return best
+
+
+def test_single_level_is_exhaustive_argmin():
+    rng = np.random.default_rng(7)
+    for seed in range(6):
+        ref = rng.integers(0, 256, (23, 31, 3), dtype=np.uint8)
+        mov = rng.integers(0, 256, (23, 31, 3), dtype=np.uint8)
+        r = oracle.align_pair(ref, mov, 1)
+        pr, pm = r["ref"], r["mov"]
+        surf = [[_brute_error(pr.tb(0), pr.eb(0), pm.tb(0), pm.eb(0), dx, dy) for dx in (-1, 0, 1)]
+                for dy in (-1, 0, 1)]
+        v, dx, dy = _first_min(surf)
+        assert r["shift"] == (dx, dy)
+        assert r["err"] == v
+        assert r["trace"][0].reshape(3, 3).tolist() == surf
+
+
+def test_trace_matches_brute_force_surface_every_level():
+    ref, mov, _ = synth.make_rect_pair(96, 64, 25, 11, 6)
+    L = 4
+    r = oracle.align_pair(ref, mov, L)
+    pr, pm = r["ref"], r["mov"]
+    base = (0, 0)
+    for l in range(L - 1, -1, -1):
+        surf = [[_brute_error(pr.tb(l), pr.eb(l), pm.tb(l), pm.eb(l), base[0] + dx, base[1] + dy)
+                 for dx in (-1, 0, 1)] for dy in (-1, 0, 1)]
+        assert r["trace"][l].reshape(3, 3).tolist() == surf
+        v, dx, dy = _first_min(surf)
+        s = (base[0] + dx, base[1] + dy)
+        assert tuple(r["level_shifts"][l]) == s
+        base = (2 * s[0], 2 * s[1])
+    assert r["shift"] == tuple(r["level_shifts"][0])
+
+
+def test_flat_image_takes_lowest_candidate_everywhere():
+    # All errors are 0, so the first candidate (-1, -1) wins at every level and the
+    # offsets compound to (-(2^L - 1), -(2^L - 1)).
+    img = np.full((64, 64, 3), 128, np.uint8)
+    for L in (1, 3, 5):
+        r = oracle.align_pair(img, img, L)
+        R = 2 ** L - 1
+        assert r["shift"] == (-R, -R)
+        assert r["err"] == 0
+
+
+def test_self_alignment_is_zero():
+    ref, _, _ = synth.make_rect_pair(160, 120, 40, 12, 0)
+    r = oracle.align_pair(ref, ref, 5)
+    assert r["shift"] == (0, 0)
+    assert r["err"] == 0
+    assert (r["level_shifts"] == 0).all()
+    # Candidate (0, 0) (index 4) has zero error at every level.
+    assert (r["trace"][:, 4] == 0).all()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_planted_translation_is_recovered(seed):
+    ref, mov, (tx, ty) = synth.make_rect_pair(256, 192, 60, 100 + seed, 20)
+    r = oracle.align_pair(ref, mov, 5)
+    assert r["shift"] == (-tx, -ty)
+
+
+def test_search_reaches_exhaustive_minimum_on_tiny_planted_images():
+    # With a unique exhaustive level-0 minimum the pyramid search lands on it.
+    ref, mov, (tx, ty) = synth.make_rect_pair(64, 48, 20, 21, 3)
+    L = 3
+    r = oracle.align_pair(ref, mov, L)
+    pr, pm = r["ref"], r["mov"]
+    R = 2 ** L - 1
+    surf = {(cx, cy): _brute_error(pr.tb(0), pr.eb(0), pm.tb(0), pm.eb(0), cx, cy)
+            for cx in range(-R, R + 1) for cy in range(-R, R + 1)}
+    best = min(surf.values())
+    winners = [c for c, v in surf.items() if v == best]
+    assert len(winners) == 1
+    assert r["shift"] == winners[0] == (-tx, -ty)
+
+
+# ---------------------------------------------------------------- stacks (Section III-B)
+
+def test_stack_is_independent_pairs_against_reference():
+    imgs, shifts, _ = synth.make_stack(96, 64, 5, 12, 31, 6)
+    out = oracle.align_stack(imgs, 4, threads=3)
+    assert out["ref_index"] == 2
+    assert tuple(out["shifts"][2]) == (0, 0) and out["errs"][2] == 0
+    for k in (0, 1, 3, 4):
+        r = oracle.align_pair(imgs[2], imgs[k], 4)
+        assert tuple(out["shifts"][k]) == r["shift"]
+        assert out["errs"][k] == r["err"]
+
+
+def test_stack_permutation_of_moving_images():
+    imgs, _, _ = synth.make_stack(80, 48, 5, 10, 32, 5)
+    a = oracle.align_stack(imgs, 3)
+    perm = [4, 3, 2, 1, 0]  # the middle (reference) stays in place
+    b = oracle.align_stack([imgs[p] for p in perm], 3)
+    assert np.array_equal(b["shifts"], a["shifts"][perm])
+    assert np.array_equal(b["errs"], a["errs"][perm])
+
+
+def test_stack_threads_do_not_change_results():
+    imgs, _, _ = synth.make_stack(64, 48, 4, 10, 33, 4)
+    a = oracle.align_stack(imgs, 3, threads=1)
+    b = oracle.align_stack(imgs, 3, threads=4)
+    assert np.array_equal(a["shifts"], b["shifts"]) and np.array_equal(a["errs"], b["errs"])
