@@ -1,0 +1,188 @@
+/*
+ * mtb.h -- C ABI of libmtb, Median Threshold Bitmap (MTB) translational
+ * alignment of exposure stacks on AMD Instinct MI355X (gfx950).
+ *
+ * The method is Ward's MTB alignment as accelerated in Alpay, Aydemir and
+ * Akyuz, "Accelerating Translational Image Registration for HDR Images on
+ * GPU" (arXiv 2007.06483): gray conversion, a 2x pyramid, a per-level
+ * 256-bin histogram median, threshold and exclusion bitmaps, and a
+ * coarse-to-fine search over the nine +-1 shifts at each level that scores a
+ * shift by XOR/AND-ing the bitmaps and counting the set pixels
+ * (Section III-A; Section III-B; Fig. 2).
+ *
+ * Conventions for every call:
+ *   - Memory.  Every pointer named d_* is device memory owned by the caller;
+ *     the library allocates no device memory and keeps no state between
+ *     calls.  Host arrays are named h_*.
+ *   - Streams.  `stream` is a hipStream_t passed as void* (NULL is the null
+ *     stream).  All device work is enqueued on it and runs asynchronously;
+ *     results are valid once the stream has reached the call's work.
+ *   - Errors.  Arguments are validated before anything is enqueued; on any
+ *     error status nothing has been enqueued.  A failed kernel launch
+ *     returns MTB_ERR_DEVICE.  No call aborts or throws.
+ *   - Images.  An RGB image is `height` rows of `width` interleaved R,G,B
+ *     bytes; row y starts at byte y * row_stride (row_stride >= 3 * width).
+ *     width * height must be below 2^31.
+ *   - Levels.  Level l of a width x height image is (width >> l) x
+ *     (height >> l); level 0 is full resolution.  1 <= levels <=
+ *     mtb_max_levels(width, height).  The search reaches shifts of up to
+ *     +-(2^levels - 1) pixels per axis.
+ *   - Shifts.  A shift (dx, dy) is what to apply to the moving image to align
+ *     it with the reference: aligned[y][x] = moving[y - dy][x - dx].
+ *   - Thread safety.  Calls are reentrant; calls on one stream that share an
+ *     output buffer are ordered by the stream.
+ */
+#ifndef MTB_H
+#define MTB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MTB_MAX_LEVELS 16 /* width * height < 2^31 allows at most 16 levels */
+#define MTB_MAX_STACK 32  /* images per mtb_align_stack call */
+
+typedef enum mtb_status {
+    MTB_OK = 0,
+    MTB_ERR_INVALID_ARG = 1, /* null pointer, size or level out of range, ... */
+    MTB_ERR_WORKSPACE = 2,   /* a buffer is smaller than its *_bytes query */
+    MTB_ERR_DEVICE = 3,      /* HIP reported an error while enqueuing */
+    MTB_ERR_UNSUPPORTED = 4  /* no usable gfx950 device */
+} mtb_status;
+
+/*
+ * Where everything lives inside the two per-image buffers.  All offsets are
+ * in bytes from the start of their buffer and are multiples of 256.
+ *
+ * Pyramid buffer (written by mtb_build_pyramid):
+ *   gray level l: level_height[l] rows of gray_pitch[l] bytes at gray_offset[l];
+ *     byte x of row y is the gray value of pixel (x, y) for x < level_width[l]
+ *     (the bytes past level_width[l] are padding with no defined value);
+ *   histogram: uint32 hist[levels][256] at hist_offset (Section III-B).
+ * Bitmaps buffer (written by mtb_bitmaps):
+ *   level l threshold bitmap T and exclusion bitmap E: each level_height[l]
+ *     rows of words_per_row[l] uint64 words at tb_offset[l] / eb_offset[l];
+ *     pixel x of row y is bit (x % 64) of word (x / 64) of the row (least
+ *     significant bit first); bits past level_width[l] are 0;
+ *   medians: int32 median[levels] at median_offset.
+ */
+typedef struct mtb_layout {
+    int32_t width, height, levels;
+    int32_t level_width[MTB_MAX_LEVELS];
+    int32_t level_height[MTB_MAX_LEVELS];
+    int32_t words_per_row[MTB_MAX_LEVELS]; /* ceil(level_width / 64) */
+    int64_t gray_offset[MTB_MAX_LEVELS];
+    int64_t gray_pitch[MTB_MAX_LEVELS]; /* 64 * words_per_row */
+    int64_t hist_offset;
+    int64_t pyramid_bytes;
+    int64_t tb_offset[MTB_MAX_LEVELS];
+    int64_t eb_offset[MTB_MAX_LEVELS];
+    int64_t median_offset;
+    int64_t bitmaps_bytes;
+} mtb_layout;
+
+/* Human-readable name of a status code (static storage; never NULL). */
+const char *mtb_status_string(mtb_status status);
+
+/* Largest level count L with (width >> (L-1)) >= 1 and (height >> (L-1)) >= 1;
+ * 0 if width or height is below 1. */
+int32_t mtb_max_levels(int32_t width, int32_t height);
+
+/* Fills *out with the buffer layout for the given size and level count.
+ * MTB_ERR_INVALID_ARG if out is NULL or the size or level count is out of range. */
+mtb_status mtb_get_layout(int32_t width, int32_t height, int32_t levels, mtb_layout *out);
+
+/* Bytes of one image's pyramid buffer / bitmaps buffer; 0 if the arguments are invalid. */
+size_t mtb_pyramid_bytes(int32_t width, int32_t height, int32_t levels);
+size_t mtb_bitmaps_bytes(int32_t width, int32_t height, int32_t levels);
+
+/* Bytes of the workspace mtb_align_pair needs (search counters); 0 if levels is out of range. */
+size_t mtb_pair_workspace_bytes(int32_t levels);
+
+/* Bytes of the workspace mtb_align_stack needs for n images; 0 if invalid. */
+size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t levels);
+
+/*
+ * Gray pyramid and per-level histograms of one RGB image (Section III-A:
+ * gray conversion and the 2x pyramid; Section III-B: 256-bin histograms of
+ * every level).  gray = (54 R + 183 G + 19 B) >> 8; each coarser level is the
+ * floor mean of 2x2 blocks of the level below, an odd last row or column
+ * being dropped.
+ *   d_rgb            device RGB image (see Images above)
+ *   d_pyramid        device buffer of pyramid_bytes >= mtb_pyramid_bytes(...)
+ *                    receiving the layout described at mtb_layout
+ * Errors: MTB_ERR_INVALID_ARG (null pointer, sizes, stride, levels),
+ *         MTB_ERR_WORKSPACE (pyramid_bytes too small), MTB_ERR_DEVICE.
+ */
+mtb_status mtb_build_pyramid(const uint8_t *d_rgb, int32_t width, int32_t height,
+                             int64_t row_stride, int32_t levels, void *d_pyramid,
+                             size_t pyramid_bytes, void *stream);
+
+/*
+ * Medians and threshold / exclusion bitmaps of every level of a pyramid
+ * (Section III-A: median threshold; Section III-B: median per histogram and
+ * exclusion bitmaps).  m = lower median of the level (element (P-1)/2 of its
+ * sorted P pixels); T = [g > m]; E = [|g - m| > exclude_range].
+ *   d_pyramid        a pyramid buffer written by mtb_build_pyramid (same size/levels)
+ *   exclude_range    half-width of the excluded band around the median, 0..255 (Ward: 4)
+ *   d_bitmaps        device buffer of bitmaps_bytes >= mtb_bitmaps_bytes(...)
+ * Errors: MTB_ERR_INVALID_ARG, MTB_ERR_WORKSPACE, MTB_ERR_DEVICE.
+ */
+mtb_status mtb_bitmaps(const void *d_pyramid, int32_t width, int32_t height, int32_t levels,
+                       int32_t exclude_range, void *d_bitmaps, size_t bitmaps_bytes,
+                       void *stream);
+
+/*
+ * Coarse-to-fine shift search between two images' bitmaps (Section III-A:
+ * +-1 tests per level, doubling between levels; Section III-B: XOR of the
+ * threshold bitmaps, AND of both exclusion bitmaps, count of set pixels).
+ * Starting from (0, 0) at the coarsest level, each level tests the nine
+ * shifts base + (ddx, ddy), ddx, ddy in {-1, 0, 1}; the error of shift c is
+ *   e(c) = #{(x, y) : (T_ref ^ S_c T_mov) & E_ref & S_c E_mov}
+ * with (S_c B)[y][x] = B[y - cy][x - cx], zero where that falls outside the
+ * image.  The lowest error wins, ties going to the lowest (ddy, ddx)
+ * (ddy-major order); the next level's base is twice the winner.
+ *   d_bm_ref, d_bm_mov   bitmaps buffers written by mtb_bitmaps
+ *   d_workspace          >= mtb_pair_workspace_bytes(levels) bytes, contents ignored
+ *   d_shift              int32[2] receives (dx, dy) at level 0
+ *   d_err                uint32[1] receives the level-0 error of that shift
+ *   d_trace              NULL or uint32[levels][9]: error of candidate
+ *                        (ddy + 1) * 3 + (ddx + 1) at each level
+ *   d_level_shifts       NULL or int32[levels][2]: the shift chosen at each level
+ * Errors: MTB_ERR_INVALID_ARG, MTB_ERR_WORKSPACE, MTB_ERR_DEVICE.
+ */
+mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t width,
+                          int32_t height, int32_t levels, void *d_workspace,
+                          size_t workspace_bytes, int32_t *d_shift, uint32_t *d_err,
+                          uint32_t *d_trace, int32_t *d_level_shifts, void *stream);
+
+/*
+ * Whole-stack alignment (Section III-B: every image is uploaded once, its
+ * pyramid and bitmaps computed once, and the stack aligned pairwise).  Every
+ * image is aligned against the reference image; each image's pyramid,
+ * histograms, medians and bitmaps are built once, and all pairs share the
+ * reference's.  The reference reports shift (0, 0) and error 0.
+ *   h_d_rgb          host array of n device pointers, one RGB image each (same size and stride)
+ *   n                1 .. MTB_MAX_STACK
+ *   ref_index        index of the reference, or -1 for n / 2
+ *   exclude_range    as for mtb_bitmaps (Ward: 4)
+ *   d_workspace      >= mtb_stack_workspace_bytes(n, width, height, levels) bytes
+ *   d_shifts         int32[n][2] receives (dx, dy) per image
+ *   d_errs           uint32[n] receives each image's level-0 error
+ *   d_trace          NULL or uint32[n][levels][9] (as for mtb_align_pair; zeros for the reference)
+ * Errors: MTB_ERR_INVALID_ARG, MTB_ERR_WORKSPACE, MTB_ERR_DEVICE.
+ */
+mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
+                           int32_t height, int64_t row_stride, int32_t levels,
+                           int32_t exclude_range, int32_t ref_index, void *d_workspace,
+                           size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                           uint32_t *d_trace, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTB_H */

@@ -1,0 +1,279 @@
+"""Python binding of libmtb: MTB translational alignment on MI355X (gfx950).
+
+Thin ctypes marshalling over the C ABI declared in include/mtb.h; the
+functions keep the C names.  Every step of the computation runs in the HIP
+kernels of libmtb.so; PyTorch only provides device memory (CUDA/HIP tensors)
+and the current stream.  There is no CPU fallback: if libmtb.so is missing,
+or no gfx950 device is usable, the calls raise.
+
+Build the library in-tree first (``python -m paper_2007_06483_amd._build`` or
+``__graft_entry__.build()``).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "MTBError",
+    "Layout",
+    "MTB_MAX_LEVELS",
+    "MTB_MAX_STACK",
+    "library_path",
+    "lib",
+    "mtb_status_string",
+    "mtb_max_levels",
+    "mtb_get_layout",
+    "mtb_pyramid_bytes",
+    "mtb_bitmaps_bytes",
+    "mtb_pair_workspace_bytes",
+    "mtb_stack_workspace_bytes",
+    "mtb_build_pyramid",
+    "mtb_bitmaps",
+    "mtb_align_pair",
+    "mtb_align_stack",
+]
+
+MTB_MAX_LEVELS = 16
+MTB_MAX_STACK = 32
+
+MTB_OK = 0
+STATUS_NAMES = {0: "MTB_OK", 1: "MTB_ERR_INVALID_ARG", 2: "MTB_ERR_WORKSPACE",
+                3: "MTB_ERR_DEVICE", 4: "MTB_ERR_UNSUPPORTED"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmtb.so")
+_lib = None
+
+
+class MTBError(RuntimeError):
+    """A libmtb call returned a status other than MTB_OK."""
+
+    def __init__(self, func: str, status: int):
+        self.status = int(status)
+        super().__init__(f"{func} failed: {STATUS_NAMES.get(self.status, self.status)}")
+
+
+class _CLayout(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("levels", ctypes.c_int32),
+        ("level_width", ctypes.c_int32 * MTB_MAX_LEVELS),
+        ("level_height", ctypes.c_int32 * MTB_MAX_LEVELS),
+        ("words_per_row", ctypes.c_int32 * MTB_MAX_LEVELS),
+        ("gray_offset", ctypes.c_int64 * MTB_MAX_LEVELS),
+        ("gray_pitch", ctypes.c_int64 * MTB_MAX_LEVELS),
+        ("hist_offset", ctypes.c_int64),
+        ("pyramid_bytes", ctypes.c_int64),
+        ("tb_offset", ctypes.c_int64 * MTB_MAX_LEVELS),
+        ("eb_offset", ctypes.c_int64 * MTB_MAX_LEVELS),
+        ("median_offset", ctypes.c_int64),
+        ("bitmaps_bytes", ctypes.c_int64),
+    ]
+
+
+class Layout:
+    """Offsets (bytes) of every level inside the pyramid and bitmaps buffers."""
+
+    def __init__(self, c: _CLayout):
+        L = c.levels
+        self.width, self.height, self.levels = c.width, c.height, L
+        self.level_width = list(c.level_width[:L])
+        self.level_height = list(c.level_height[:L])
+        self.words_per_row = list(c.words_per_row[:L])
+        self.gray_offset = list(c.gray_offset[:L])
+        self.gray_pitch = list(c.gray_pitch[:L])
+        self.hist_offset = c.hist_offset
+        self.pyramid_bytes = c.pyramid_bytes
+        self.tb_offset = list(c.tb_offset[:L])
+        self.eb_offset = list(c.eb_offset[:L])
+        self.median_offset = c.median_offset
+        self.bitmaps_bytes = c.bitmaps_bytes
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded libmtb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libmtb.so is not built ({_LIB_PATH}); run paper_2007_06483_amd._build.build()")
+    L = ctypes.CDLL(_LIB_PATH)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.mtb_status_string.argtypes = [ctypes.c_int]
+    L.mtb_status_string.restype = ctypes.c_char_p
+    L.mtb_max_levels.argtypes = [i32, i32]
+    L.mtb_max_levels.restype = i32
+    L.mtb_get_layout.argtypes = [i32, i32, i32, ctypes.POINTER(_CLayout)]
+    L.mtb_get_layout.restype = ctypes.c_int
+    for f in ("mtb_pyramid_bytes", "mtb_bitmaps_bytes"):
+        getattr(L, f).argtypes = [i32, i32, i32]
+        getattr(L, f).restype = sz
+    L.mtb_pair_workspace_bytes.argtypes = [i32]
+    L.mtb_pair_workspace_bytes.restype = sz
+    L.mtb_stack_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.mtb_stack_workspace_bytes.restype = sz
+    L.mtb_build_pyramid.argtypes = [P, i32, i32, i64, i32, P, sz, P]
+    L.mtb_build_pyramid.restype = ctypes.c_int
+    L.mtb_bitmaps.argtypes = [P, i32, i32, i32, i32, P, sz, P]
+    L.mtb_bitmaps.restype = ctypes.c_int
+    L.mtb_align_pair.argtypes = [P, P, i32, i32, i32, P, sz, P, P, P, P, P]
+    L.mtb_align_pair.restype = ctypes.c_int
+    L.mtb_align_stack.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, i32, i32, P, sz, P, P, P, P]
+    L.mtb_align_stack.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(func: str, status: int):
+    if status != MTB_OK:
+        raise MTBError(func, status)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _device_u8(t: torch.Tensor, what: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.uint8:
+        raise TypeError(f"{what} must be a uint8 tensor on a GPU")
+
+
+def _rgb_geometry(img: torch.Tensor):
+    """(H, W, 3) uint8 device tensor with packed pixels -> (W, H, row_stride_bytes)."""
+    _device_u8(img, "image")
+    if img.dim() != 3 or img.shape[2] != 3 or img.stride(2) != 1 or img.stride(1) != 3:
+        raise ValueError("image must be (H, W, 3) with interleaved R,G,B bytes")
+    return int(img.shape[1]), int(img.shape[0]), int(img.stride(0))
+
+
+def mtb_status_string(status: int) -> str:
+    return lib().mtb_status_string(int(status)).decode()
+
+
+def mtb_max_levels(width: int, height: int) -> int:
+    return int(lib().mtb_max_levels(width, height))
+
+
+def mtb_get_layout(width: int, height: int, levels: int) -> Layout:
+    c = _CLayout()
+    _check("mtb_get_layout", lib().mtb_get_layout(width, height, levels, ctypes.byref(c)))
+    return Layout(c)
+
+
+def mtb_pyramid_bytes(width: int, height: int, levels: int) -> int:
+    return int(lib().mtb_pyramid_bytes(width, height, levels))
+
+
+def mtb_bitmaps_bytes(width: int, height: int, levels: int) -> int:
+    return int(lib().mtb_bitmaps_bytes(width, height, levels))
+
+
+def mtb_pair_workspace_bytes(levels: int) -> int:
+    return int(lib().mtb_pair_workspace_bytes(levels))
+
+
+def mtb_stack_workspace_bytes(n: int, width: int, height: int, levels: int) -> int:
+    return int(lib().mtb_stack_workspace_bytes(n, width, height, levels))
+
+
+def _buffer(nbytes: int, device, out=None) -> torch.Tensor:
+    if out is None:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    _device_u8(out, "output buffer")
+    return out
+
+
+def mtb_build_pyramid(rgb: torch.Tensor, levels: int, pyramid: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+    """Gray pyramid and histograms of one (H, W, 3) RGB image; returns the pyramid buffer."""
+    W, H, stride = _rgb_geometry(rgb)
+    need = mtb_pyramid_bytes(W, H, levels)
+    pyramid = _buffer(max(need, 1), rgb.device, pyramid)
+    _check("mtb_build_pyramid",
+           lib().mtb_build_pyramid(_ptr(rgb), W, H, stride, levels, _ptr(pyramid),
+                                   pyramid.numel(), _stream(stream)))
+    return pyramid
+
+
+def mtb_bitmaps(pyramid: torch.Tensor, width: int, height: int, levels: int, exclude_range: int = 4,
+                bitmaps: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Medians and packed threshold/exclusion bitmaps of a pyramid; returns the bitmaps buffer."""
+    _device_u8(pyramid, "pyramid")
+    need = mtb_bitmaps_bytes(width, height, levels)
+    bitmaps = _buffer(max(need, 1), pyramid.device, bitmaps)
+    _check("mtb_bitmaps",
+           lib().mtb_bitmaps(_ptr(pyramid), width, height, levels, exclude_range, _ptr(bitmaps),
+                             bitmaps.numel(), _stream(stream)))
+    return bitmaps
+
+
+def mtb_align_pair(bm_ref: torch.Tensor, bm_mov: torch.Tensor, width: int, height: int,
+                   levels: int, workspace: torch.Tensor | None = None, trace: bool = False,
+                   level_shifts: bool = False, stream=None) -> dict:
+    """Coarse-to-fine search of the moving bitmaps against the reference's.
+
+    Returns device tensors ``shift`` int32[2] (dx, dy), ``err`` int32[1] (the uint32
+    level-0 count, below 2^31) and optionally ``trace`` int32[levels][9] and
+    ``level_shifts`` int32[levels][2].
+    """
+    _device_u8(bm_ref, "bm_ref")
+    _device_u8(bm_mov, "bm_mov")
+    dev = bm_ref.device
+    workspace = _buffer(max(mtb_pair_workspace_bytes(levels), 1), dev, workspace)
+    shift = torch.empty(2, dtype=torch.int32, device=dev)
+    err = torch.empty(1, dtype=torch.int32, device=dev)
+    tr = torch.empty((levels, 9), dtype=torch.int32, device=dev) if trace else None
+    ls = torch.empty((levels, 2), dtype=torch.int32, device=dev) if level_shifts else None
+    _check("mtb_align_pair",
+           lib().mtb_align_pair(_ptr(bm_ref), _ptr(bm_mov), width, height, levels, _ptr(workspace),
+                                workspace.numel(), _ptr(shift), _ptr(err), _ptr(tr), _ptr(ls),
+                                _stream(stream)))
+    return {"shift": shift, "err": err, "trace": tr, "level_shifts": ls}
+
+
+def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int = -1,
+                    workspace: torch.Tensor | None = None, trace: bool = False, shifts=None,
+                    errs=None, stream=None) -> dict:
+    """Align every (H, W, 3) image of a stack against the reference (n // 2 by default).
+
+    Returns device tensors ``shifts`` int32[n][2], ``errs`` int32[n] (the uint32
+    counts, which stay below 2^31) and, with trace=True, ``trace`` int32[n][levels][9].
+    """
+    n = len(images)
+    if not 1 <= n <= MTB_MAX_STACK:
+        raise ValueError(f"a stack holds 1..{MTB_MAX_STACK} images")
+    W, H, stride = _rgb_geometry(images[0])
+    for im in images:
+        if _rgb_geometry(im) != (W, H, stride) or im.device != images[0].device:
+            raise ValueError("all images of a stack must share size, stride and device")
+    dev = images[0].device
+    need = mtb_stack_workspace_bytes(n, W, H, levels)
+    workspace = _buffer(max(need, 1), dev, workspace)
+    if shifts is None:
+        shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    if errs is None:
+        errs = torch.empty(n, dtype=torch.int32, device=dev)
+    tr = torch.empty((n, levels, 9), dtype=torch.int32, device=dev) if trace else None
+    ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in images])
+    _check("mtb_align_stack",
+           lib().mtb_align_stack(ptrs, n, W, H, stride, levels, exclude_range, ref_index,
+                                 _ptr(workspace), workspace.numel(), _ptr(shifts), _ptr(errs),
+                                 _ptr(tr), _stream(stream)))
+    return {"shifts": shifts, "errs": errs, "trace": tr, "workspace": workspace}

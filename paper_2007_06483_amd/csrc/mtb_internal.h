@@ -1,0 +1,135 @@
+// mtb_internal.h -- layout arithmetic and kernel argument blocks shared by the
+// HIP kernels (mtb_kernels.hip) and the C-ABI entry points (mtb_api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mtb.h"
+
+namespace mtb {
+
+constexpr int kMaxLevels = MTB_MAX_LEVELS;
+constexpr int kMaxStack = MTB_MAX_STACK;
+constexpr int kAlign = 256;
+
+// Pass 1 fuses this many pyramid levels per 64x64 tile (64 = 2^(kFused-1)).
+constexpr int kFused = 7;
+constexpr int kTile = 64;
+
+// Search counters are spread over this many copies per (pair, level) so that
+// concurrent workgroups do not all add into the same nine words.
+constexpr int kCopies = 8;
+// Per pair and level: kCopies x 9 uint32 counters.
+constexpr int kCounterWords = kCopies * 9;
+
+inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Geometry of one pyramid level, with offsets into the per-image buffers.
+struct LevelGeom {
+    int32_t w, h;         // level size in pixels
+    int32_t wpr;          // uint64 words per bitmap row = ceil(w / 64)
+    int32_t pad_;
+    int64_t gray_off;     // bytes, pyramid buffer
+    int64_t gray_pitch;   // bytes = 64 * wpr
+    int64_t tb_off;       // bytes, bitmaps buffer
+    int64_t eb_off;       // bytes, bitmaps buffer
+};
+
+struct Geometry {
+    int32_t W, H, L, pad_;
+    LevelGeom lv[kMaxLevels];
+    int64_t hist_off;       // uint32[L][256] in the pyramid buffer
+    int64_t pyramid_bytes;
+    int64_t med_off;        // int32[L] in the bitmaps buffer
+    int64_t bitmaps_bytes;
+};
+
+// Returns false if the size or level count is out of range.
+bool make_geometry(int32_t W, int32_t H, int32_t L, Geometry *g);
+int32_t max_levels(int32_t W, int32_t H);
+
+// ------------------------------------------------------------------ pass 1
+
+struct PyramidArgs {
+    const uint8_t *rgb[kMaxStack];
+    uint8_t *pyr[kMaxStack];
+    int64_t stride;          // bytes between RGB rows
+    int32_t n;               // images
+    int32_t tiles_x, tiles_y;
+    int32_t tiles_per_block; // contiguous tiles handled by one workgroup
+    int32_t aligned;         // 1 if every RGB row start is 4-byte aligned
+    int32_t pad_;
+    Geometry g;
+};
+
+// Levels kFused..L-1 are built from level kFused-1 by one workgroup per image.
+struct CoarsePyramidArgs {
+    uint8_t *pyr[kMaxStack];
+    int32_t n, pad_;
+    Geometry g;
+};
+
+// ------------------------------------------------------------------ pass 2
+
+// The bitmaps pass walks each level as a flat run of 64-pixel words, in
+// chunks of kChunkWords words (kChunkWords * 64 gray bytes) per wavefront.
+constexpr int kChunkWords = 16;
+
+struct BitmapArgs {
+    const uint8_t *pyr[kMaxStack];
+    uint8_t *bm[kMaxStack];
+    int32_t n;
+    int32_t exclude;
+    int64_t chunk_start[kMaxLevels + 1];  // first chunk of each level within one image
+    Geometry g;
+};
+
+// ------------------------------------------------------------------ search
+
+// Per pair the search state is: counters uint32[L][kCounterWords], then
+// base int32[L][2] (the centre of each level's nine candidates).
+inline int64_t pair_state_words(int32_t L) { return (int64_t)L * kCounterWords + 2 * L; }
+
+struct SearchArgs {
+    const uint8_t *ref[kMaxStack];   // bitmaps buffer of each pair's reference
+    const uint8_t *mov[kMaxStack];   // bitmaps buffer of each pair's moving image
+    uint32_t *state;                 // pair p's state at state + p * state_stride
+    int64_t state_stride;            // uint32 words
+    int32_t npairs;
+    int32_t level;                   // fine kernel: the level searched
+    int32_t coarse_lo;               // coarse kernel: lowest level it searches
+    int32_t rows_per_unit;           // rows per wavefront work unit
+    int32_t units_x;                 // 64-dword column strips per row (current level)
+    int32_t units_per_pair;          // work units per pair (current level)
+    Geometry g;
+};
+
+struct FinalizeArgs {
+    const uint32_t *state;
+    int64_t state_stride;
+    int32_t npairs;
+    int32_t L;
+    int32_t pair_image[kMaxStack];   // output row of each pair (stack index)
+    int32_t n_out;                   // rows of the outputs
+    int32_t pad_;
+    int32_t *shifts;                 // [n_out][2]
+    uint32_t *errs;                  // [n_out]
+    uint32_t *trace;                 // NULL or [n_out][L][9]
+    int32_t *level_shifts;           // NULL or [n_out][L][2]
+};
+
+struct ZeroArgs {
+    uint32_t *ptr[2 * kMaxStack + 1];
+    int64_t words[2 * kMaxStack + 1];
+    int32_t count;
+};
+
+// Launch helpers (mtb_kernels.hip).  Each returns the hipError_t of its launches.
+hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);
+hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s);
+hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s);
+hipError_t launch_search(SearchArgs a, int coarse_lo, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
+
+}  // namespace mtb

@@ -1,0 +1,54 @@
+"""Host-side decoding of libmtb's device buffers into plain numpy arrays.
+
+Only layout arithmetic (offsets from mtb_get_layout, bit unpacking); no part
+of the alignment method.  Used by the parity tests to compare every
+intermediate with the oracle.
+"""
+
+import numpy as np
+
+
+def gray_levels(buf: np.ndarray, layout):
+    out = []
+    for l in range(layout.levels):
+        w, h = layout.level_width[l], layout.level_height[l]
+        off, pitch = layout.gray_offset[l], layout.gray_pitch[l]
+        out.append(buf[off:off + pitch * h].reshape(h, pitch)[:, :w])
+    return out
+
+
+def histograms(buf: np.ndarray, layout) -> np.ndarray:
+    off = layout.hist_offset
+    return buf[off:off + 1024 * layout.levels].view(np.uint32).reshape(layout.levels, 256)
+
+
+def medians(bm: np.ndarray, layout) -> np.ndarray:
+    off = layout.median_offset
+    return bm[off:off + 4 * layout.levels].view(np.int32)
+
+
+def _plane(bm, off, w, h, wpr):
+    words = bm[off:off + 8 * wpr * h].view(np.uint64).reshape(h, wpr)
+    bits = np.unpackbits(words.view(np.uint8), bitorder="little").reshape(h, wpr * 64)
+    return bits[:, :w], bits[:, w:]
+
+
+def bitmaps(bm: np.ndarray, layout):
+    """Per level (T, E, T_pad_bits, E_pad_bits) as 0/1 uint8 arrays."""
+    out = []
+    for l in range(layout.levels):
+        w, h, wpr = layout.level_width[l], layout.level_height[l], layout.words_per_row[l]
+        t, tp = _plane(bm, layout.tb_offset[l], w, h, wpr)
+        e, ep = _plane(bm, layout.eb_offset[l], w, h, wpr)
+        out.append((t, e, tp, ep))
+    return out
+
+
+def stack_workspace(ws: np.ndarray, ws_ptr: int, n: int, layout):
+    """Split an mtb_align_stack workspace into per-image (pyramid, bitmaps) byte arrays."""
+    start = (-ws_ptr) % 256
+    P, B = layout.pyramid_bytes, layout.bitmaps_bytes
+    pyr = [ws[start + i * P:start + (i + 1) * P] for i in range(n)]
+    bm0 = start + n * P
+    bms = [ws[bm0 + i * B:bm0 + (i + 1) * B] for i in range(n)]
+    return pyr, bms

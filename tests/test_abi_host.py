@@ -1,0 +1,186 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, reports the documented layout, and rejects bad arguments before
+enqueuing anything.  No GPU is needed (no call here reaches a kernel)."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mtb.h")
+
+
+@pytest.fixture(scope="module")
+def mtb():
+    import paper_2007_06483_amd as m
+
+    if not os.path.exists(m.library_path()):
+        from paper_2007_06483_amd import _build
+
+        _build.build()
+    m.lib()
+    return m
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mtb_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for f in ("mtb_build_pyramid", "mtb_bitmaps", "mtb_align_pair", "mtb_align_stack"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(mtb):
+    lib = ctypes.CDLL(mtb.library_path())
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", mtb.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (mtb_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_status_strings(mtb):
+    assert mtb.mtb_status_string(0) == "MTB_OK"
+    assert mtb.mtb_status_string(2) == "MTB_ERR_WORKSPACE"
+    assert mtb.mtb_status_string(99) == "MTB_ERR_UNKNOWN"
+
+
+@pytest.mark.parametrize("w,h,L", [(1, 1, 1), (2, 1, 1), (6000, 4000, 12), (512, 384, 9),
+                                   (46340, 46340, 16), (1 << 30, 1, 1), (3, 1 << 20, 2)])
+def test_max_levels(mtb, w, h, L):
+    assert mtb.mtb_max_levels(w, h) == L
+
+
+def test_max_levels_rejects_empty(mtb):
+    assert mtb.mtb_max_levels(0, 5) == 0
+    assert mtb.mtb_max_levels(5, -1) == 0
+
+
+@pytest.mark.parametrize("w,h,L", [(6000, 4000, 7), (641, 479, 7), (1, 1, 1), (65, 3, 2)])
+def test_layout_is_consistent(mtb, w, h, L):
+    lay = mtb.mtb_get_layout(w, h, L)
+    assert lay.levels == L
+    end = 0
+    for l in range(L):
+        assert lay.level_width[l] == w >> l and lay.level_height[l] == h >> l
+        assert lay.words_per_row[l] == -(-(w >> l) // 64)
+        assert lay.gray_pitch[l] == 64 * lay.words_per_row[l]
+        assert lay.gray_offset[l] % 256 == 0 and lay.gray_offset[l] >= end
+        end = lay.gray_offset[l] + lay.gray_pitch[l] * lay.level_height[l]
+    assert lay.hist_offset >= end and lay.hist_offset % 256 == 0
+    assert lay.pyramid_bytes >= lay.hist_offset + 1024 * L
+    assert lay.pyramid_bytes == mtb.mtb_pyramid_bytes(w, h, L)
+    end = 0
+    for l in range(L):
+        plane = 8 * lay.words_per_row[l] * lay.level_height[l]
+        for off in (lay.tb_offset[l], lay.eb_offset[l]):
+            assert off % 256 == 0 and off >= end
+            end = off + plane
+    assert lay.median_offset >= end
+    assert lay.bitmaps_bytes >= lay.median_offset + 4 * L
+    assert lay.bitmaps_bytes == mtb.mtb_bitmaps_bytes(w, h, L)
+
+
+def test_workspace_sizes(mtb):
+    P, B = mtb.mtb_pyramid_bytes(6000, 4000, 7), mtb.mtb_bitmaps_bytes(6000, 4000, 7)
+    ws = mtb.mtb_stack_workspace_bytes(7, 6000, 4000, 7)
+    assert ws >= 7 * (P + B) + 6 * mtb.mtb_pair_workspace_bytes(7)
+    assert mtb.mtb_pair_workspace_bytes(7) >= 4 * (7 * 72 + 14)
+    assert mtb.mtb_stack_workspace_bytes(0, 10, 10, 1) == 0
+    assert mtb.mtb_stack_workspace_bytes(33, 10, 10, 1) == 0
+    assert mtb.mtb_pair_workspace_bytes(0) == 0 and mtb.mtb_pair_workspace_bytes(17) == 0
+
+
+@pytest.mark.parametrize("w,h,L", [(0, 5, 1), (5, 0, 1), (10, 10, 0), (10, 10, 5), (1 << 16, 1 << 15, 1)])
+def test_invalid_sizes_rejected(mtb, w, h, L):
+    assert mtb.mtb_pyramid_bytes(w, h, L) == 0
+    assert mtb.mtb_bitmaps_bytes(w, h, L) == 0
+    from paper_2007_06483_amd import MTBError
+
+    with pytest.raises(MTBError) as e:
+        mtb.mtb_get_layout(w, h, L)
+    assert e.value.status == 1
+
+
+# Validation happens before anything touches a device, so these calls pass fake
+# (never dereferenced) addresses and must come back with the documented status.
+FAKE = ctypes.c_void_p(0x1000)
+NULL = None
+
+
+def _c(mtb):
+    return mtb.lib()
+
+
+def test_build_pyramid_validation(mtb):
+    L = _c(mtb)
+    need = mtb.mtb_pyramid_bytes(64, 48, 3)
+    assert L.mtb_build_pyramid(NULL, 64, 48, 192, 3, FAKE, need, NULL) == 1
+    assert L.mtb_build_pyramid(FAKE, 64, 48, 192, 3, NULL, need, NULL) == 1
+    assert L.mtb_build_pyramid(FAKE, 64, 48, 191, 3, FAKE, need, NULL) == 1   # stride < 3W
+    assert L.mtb_build_pyramid(FAKE, 64, 48, 192, 7, FAKE, need, NULL) == 1   # too many levels
+    assert L.mtb_build_pyramid(FAKE, 64, 48, 192, 0, FAKE, need, NULL) == 1
+    assert L.mtb_build_pyramid(FAKE, 64, 48, 192, 3, FAKE, need - 1, NULL) == 2
+
+
+def test_bitmaps_validation(mtb):
+    L = _c(mtb)
+    need = mtb.mtb_bitmaps_bytes(64, 48, 3)
+    assert L.mtb_bitmaps(NULL, 64, 48, 3, 4, FAKE, need, NULL) == 1
+    assert L.mtb_bitmaps(FAKE, 64, 48, 3, -1, FAKE, need, NULL) == 1
+    assert L.mtb_bitmaps(FAKE, 64, 48, 3, 256, FAKE, need, NULL) == 1
+    assert L.mtb_bitmaps(FAKE, 64, 48, 3, 4, FAKE, need - 1, NULL) == 2
+
+
+def test_align_pair_validation(mtb):
+    L = _c(mtb)
+    ws = mtb.mtb_pair_workspace_bytes(3)
+    args = [FAKE, FAKE, 64, 48, 3, FAKE, ws, FAKE, FAKE, NULL, NULL, NULL]
+    for i in (0, 1, 5, 7, 8):
+        bad = list(args)
+        bad[i] = NULL
+        assert L.mtb_align_pair(*bad) == 1, i
+    bad = list(args)
+    bad[6] = ws - 1
+    assert L.mtb_align_pair(*bad) == 2
+    bad = list(args)
+    bad[4] = 7
+    assert L.mtb_align_pair(*bad) == 1
+
+
+def test_align_stack_validation(mtb):
+    L = _c(mtb)
+    n = 3
+    ptrs = (ctypes.c_void_p * n)(0x1000, 0x2000, 0x3000)
+    ws = mtb.mtb_stack_workspace_bytes(n, 64, 48, 3)
+    args = [ptrs, n, 64, 48, 192, 3, 4, -1, FAKE, ws, FAKE, FAKE, NULL, NULL]
+    assert L.mtb_align_stack(*[NULL if i == 0 else a for i, a in enumerate(args)]) == 1
+    for i, v in ((1, 0), (1, 33), (4, 100), (5, 9), (6, -2), (7, 3), (8, NULL), (10, NULL), (11, NULL)):
+        bad = list(args)
+        bad[i] = v
+        assert L.mtb_align_stack(*bad) == 1, (i, v)
+    nullp = (ctypes.c_void_p * n)(0x1000, 0, 0x3000)
+    bad = list(args)
+    bad[0] = nullp
+    assert L.mtb_align_stack(*bad) == 1
+    bad = list(args)
+    bad[9] = ws - 1
+    assert L.mtb_align_stack(*bad) == 2
+
+
+def test_valid_call_without_gpu_is_unsupported(mtb):
+    import torch
+
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible; this checks the no-device path")
+    L = _c(mtb)
+    need = mtb.mtb_pyramid_bytes(64, 48, 3)
+    assert L.mtb_build_pyramid(FAKE, 64, 48, 192, 3, FAKE, need, NULL) == 4

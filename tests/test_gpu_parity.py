@@ -1,0 +1,235 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every intermediate is compared element by element: gray levels, histograms,
+medians, unpacked threshold/exclusion bitmaps (and their zero padding bits),
+per-level candidate errors, per-level shifts, final shifts and errors.  The
+method is integer-only, so the tolerance is zero everywhere.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from mtb_decode import bitmaps, gray_levels, histograms, medians, stack_workspace
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mtb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_06483_amd as m
+
+    m.lib()
+    return m
+
+
+DEV = "cuda:0"
+
+
+def _noise(h, w, seed):
+    return np.random.default_rng(seed).integers(0, 256, (h, w, 3), dtype=np.uint8)
+
+
+def _to_dev(img):
+    return torch.from_numpy(np.ascontiguousarray(img)).to(DEV)
+
+
+def _strided_dev(img, extra, offset):
+    """Device view of img whose rows are 3W + extra bytes apart, starting offset bytes in."""
+    h, w, _ = img.shape
+    stride = 3 * w + extra
+    buf = np.random.default_rng(99).integers(0, 256, offset + stride * h + 8, dtype=np.uint8)
+    rows = buf[offset:offset + stride * h].reshape(h, stride)
+    rows[:, :3 * w] = img.reshape(h, 3 * w)
+    d = torch.from_numpy(buf).to(DEV)
+    return torch.as_strided(d, (h, w, 3), (stride, 3, 1), offset)
+
+
+def _check_pyramid(mtb, d_img, img, L):
+    h, w, _ = img.shape
+    lay = mtb.mtb_get_layout(w, h, L)
+    pyr = mtb.mtb_build_pyramid(d_img, L)
+    bm = mtb.mtb_bitmaps(pyr, w, h, L, 4)
+    torch.cuda.synchronize()
+    pyr_h, bm_h = pyr.cpu().numpy(), bm.cpu().numpy()
+    want = oracle.pyramid(img, L)
+    for l, g in enumerate(gray_levels(pyr_h, lay)):
+        assert np.array_equal(g, want.gray(l)), f"gray level {l}"
+    assert np.array_equal(histograms(pyr_h, lay), want.hist)
+    assert np.array_equal(medians(bm_h, lay), want.median)
+    for l, (t, e, tp, ep) in enumerate(bitmaps(bm_h, lay)):
+        assert np.array_equal(t, want.tb(l)), f"T level {l}"
+        assert np.array_equal(e, want.eb(l)), f"E level {l}"
+        assert not tp.any() and not ep.any(), f"padding bits set at level {l}"
+    return pyr, bm
+
+
+# Sizes: several 64x64 tiles with ragged right/bottom tiles, odd sizes, single rows
+# and columns, more than the seven levels fused in one pass, and the largest level count.
+SIZES = [
+    (512, 384, 5), (641, 479, 7), (130, 70, 7), (1000, 700, 9), (257, 129, 8),
+    (1, 97, 1), (97, 1, 1), (3, 5, 1), (5, 3, 2), (64, 64, 7), (65, 63, 6), (2048, 33, 6),
+    (300, 4000, 9), (2100, 2050, 12),
+]
+
+
+@pytest.mark.parametrize("w,h,L", SIZES)
+def test_pyramid_and_bitmaps_match_oracle(mtb, w, h, L):
+    img = _noise(h, w, w * 7 + h)
+    _check_pyramid(mtb, _to_dev(img), img, L)
+
+
+@pytest.mark.parametrize("w,h,L", [(512, 384, 5), (331, 217, 6)])
+def test_scene_pyramid_matches_oracle(mtb, w, h, L):
+    ref, mov, _ = synth.make_rect_pair(w, h, 30, 5, 10)
+    for img in (ref, mov):
+        _check_pyramid(mtb, _to_dev(img), img, L)
+
+
+@pytest.mark.parametrize("extra,offset", [(1, 0), (5, 3), (64, 1), (0, 2)])
+def test_pyramid_with_unaligned_rows(mtb, extra, offset):
+    img = _noise(77, 133, 42 + extra)
+    _check_pyramid(mtb, _strided_dev(img, extra, offset), img, 5)
+
+
+def test_saturated_and_flat_images(mtb):
+    for val in (0, 255, 128):
+        img = np.full((150, 200, 3), val, np.uint8)
+        _check_pyramid(mtb, _to_dev(img), img, 6)
+    img = _noise(150, 200, 3)
+    img[:, :120] = 255
+    _check_pyramid(mtb, _to_dev(img), img, 6)
+
+
+def _check_pair(mtb, ref, mov, L):
+    h, w, _ = ref.shape
+    want = oracle.align_pair(ref, mov, L)
+    pr = mtb.mtb_build_pyramid(_to_dev(ref), L)
+    pm = mtb.mtb_build_pyramid(_to_dev(mov), L)
+    br = mtb.mtb_bitmaps(pr, w, h, L)
+    bmv = mtb.mtb_bitmaps(pm, w, h, L)
+    got = mtb.mtb_align_pair(br, bmv, w, h, L, trace=True, level_shifts=True)
+    torch.cuda.synchronize()
+    assert tuple(got["shift"].cpu().tolist()) == want["shift"]
+    assert int(got["err"].cpu()[0]) == want["err"]
+    assert np.array_equal(got["trace"].cpu().numpy().astype(np.int64), want["trace"])
+    assert np.array_equal(got["level_shifts"].cpu().numpy(), want["level_shifts"])
+    return want
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_align_pair_rect_scenes(mtb, seed):
+    ref, mov, t = synth.make_rect_pair(400 + 37 * seed, 300 - 11 * seed, 50, 200 + seed, 25)
+    want = _check_pair(mtb, ref, mov, 5)
+    assert want["shift"] == (-t[0], -t[1])
+
+
+def test_align_pair_blob_workload_512x384(mtb):
+    (imgs, _, _), = synth.workload("pair_512x384").stacks
+    _check_pair(mtb, imgs[0], imgs[1], 5)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 7, 8, 9])
+def test_align_pair_level_counts(mtb, L):
+    ref, mov, _ = synth.make_rect_pair(700, 520, 60, 300 + L, 40)
+    _check_pair(mtb, ref, mov, L)
+
+
+def test_align_pair_degenerate(mtb):
+    flat = np.full((96, 128, 3), 77, np.uint8)
+    want = _check_pair(mtb, flat, flat, 4)
+    assert want["shift"] == (-15, -15) and want["err"] == 0
+    ref, _, _ = synth.make_rect_pair(200, 150, 30, 17, 0)
+    want = _check_pair(mtb, ref, ref, 5)
+    assert want["shift"] == (0, 0)
+    _check_pair(mtb, _noise(1, 300, 1), _noise(1, 300, 2), 1)
+    _check_pair(mtb, _noise(301, 2, 3), _noise(301, 2, 4), 2)
+
+
+def _check_stack(mtb, imgs, L, ref_index=None, exclude=4):
+    want = oracle.align_stack(imgs, L, ref_index=ref_index, exclude=exclude, threads=4, keep=True)
+    d = [_to_dev(im) for im in imgs]
+    got = mtb.mtb_align_stack(d, L, exclude_range=exclude,
+                              ref_index=-1 if ref_index is None else ref_index, trace=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(got["shifts"].cpu().numpy(), want["shifts"])
+    assert np.array_equal(got["errs"].cpu().numpy().astype(np.int64), want["errs"])
+    tr = got["trace"].cpu().numpy().astype(np.int64)
+    for k, r in want["pairs"].items():
+        assert np.array_equal(tr[k], r["trace"]), f"trace of image {k}"
+    assert not tr[want["ref_index"]].any()
+    return got, want
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_align_stack_matches_oracle(mtb, n):
+    imgs, _, _ = synth.make_stack(333, 251, n, 40, 500 + n, 30, sat_frac=0.05)
+    _check_stack(mtb, imgs, 6)
+
+
+def test_align_stack_reference_choice_and_exclusion(mtb):
+    imgs, _, _ = synth.make_stack(256, 200, 4, 30, 77, 20)
+    _check_stack(mtb, imgs, 5, ref_index=0)
+    _check_stack(mtb, imgs, 5, ref_index=3, exclude=0)
+    _check_stack(mtb, imgs, 5, ref_index=2, exclude=12)
+
+
+def test_stack_intermediates_match_oracle(mtb):
+    imgs, _, _ = synth.make_stack(321, 203, 3, 30, 88, 15, sat_frac=0.05)
+    L = 6
+    got, want = _check_stack(mtb, imgs, L)
+    lay = mtb.mtb_get_layout(321, 203, L)
+    ws = got["workspace"]
+    pyrs, bms = stack_workspace(ws.cpu().numpy(), ws.data_ptr(), 3, lay)
+    for i, p in enumerate(want["pyramids"]):
+        for l, g in enumerate(gray_levels(pyrs[i], lay)):
+            assert np.array_equal(g, p.gray(l))
+        assert np.array_equal(histograms(pyrs[i], lay), p.hist)
+        assert np.array_equal(medians(bms[i], lay), p.median)
+        for l, (t, e, tp, ep) in enumerate(bitmaps(bms[i], lay)):
+            assert np.array_equal(t, p.tb(l)) and np.array_equal(e, p.eb(l))
+            assert not tp.any() and not ep.any()
+
+
+def test_repeated_runs_are_bit_identical(mtb):
+    imgs, _, _ = synth.make_stack(800, 600, 5, 60, 91, 40, sat_frac=0.05)
+    d = [_to_dev(im) for im in imgs]
+    a = mtb.mtb_align_stack(d, 7, trace=True)
+    b = mtb.mtb_align_stack(d, 7, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a["shifts"], b["shifts"]) and torch.equal(a["errs"], b["errs"])
+    assert torch.equal(a["trace"], b["trace"])
+    lay = mtb.mtb_get_layout(800, 600, 7)
+    n = 5
+    # Compare every defined byte of the pyramids and bitmaps (row padding and the
+    # gaps between aligned planes hold no defined value).
+    pa, ba = stack_workspace(a["workspace"].cpu().numpy(), a["workspace"].data_ptr(), n, lay)
+    pb, bb = stack_workspace(b["workspace"].cpu().numpy(), b["workspace"].data_ptr(), n, lay)
+    for i in range(n):
+        for ga, gb in zip(gray_levels(pa[i], lay), gray_levels(pb[i], lay)):
+            assert np.array_equal(ga, gb)
+        assert np.array_equal(histograms(pa[i], lay), histograms(pb[i], lay))
+        assert np.array_equal(medians(ba[i], lay), medians(bb[i], lay))
+        for l in range(lay.levels):
+            for off in (lay.tb_offset[l], lay.eb_offset[l]):
+                size = 8 * lay.words_per_row[l] * lay.level_height[l]
+                assert np.array_equal(ba[i][off:off + size], bb[i][off:off + size])
+
+
+@pytest.mark.timeout(900)
+def test_full_size_pair_4096x3072(mtb):
+    w = synth.workload("pair_4096x3072")
+    (imgs, _, _), = w.stacks
+    _check_stack(mtb, imgs, w.levels, ref_index=0)
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_stack_7x6000x4000(mtb):
+    w = synth.workload("stack7_6000x4000")
+    (imgs, _, ref), = w.stacks
+    _check_stack(mtb, imgs, w.levels, ref_index=ref)
