@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Throughput of MTB exposure-stack alignment on one MI355X.
+
+One step aligns the whole stack through the C ABI (mtb_align_stack): gray
+conversion, pyramid, histograms, medians, threshold/exclusion bitmaps and the
+coarse-to-fine nine-candidate search of every non-reference image against the
+middle one.  The inputs are resident in HBM before timing starts.
+
+Workload (default): seven 6000x4000 RGB exposures 2^-3..2^3, 7 levels (+-127 px),
+synthetic blob scene with 5% pooled saturation, moving images translated by
+seeded shifts in [-100, 100].  Megapixels count every input image.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2007_06483_amd", "csrc", "mtb_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_stack7_6000x4000.json")
+METRIC = "megapixels aligned/sec (full pyramid) + HBM GB/s; served p50/p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def level_sizes(lay):
+    return [(lay.level_width[l], lay.level_height[l], lay.words_per_row[l]) for l in range(lay.levels)]
+
+
+def algorithmic_bytes(lay, n_images, n_pairs):
+    """Bytes each kernel of one stack alignment must move (staged design, per launch).
+
+    k_pyramid: RGB read (3 B/px) + every gray level written once.
+    k_bitmaps: every gray level read once + T and E words written.
+    search:    per pair and level, the four bitmaps read once.
+    """
+    W, H = lay.width, lay.height
+    lv = level_sizes(lay)
+    gray = sum(w * h for w, h, _ in lv)
+    maps = sum(8 * wpr * h for _, h, wpr in lv)  # one bitmap plane, all levels
+    per = {
+        "k_pyramid": n_images * (3 * W * H + gray),
+        "k_bitmaps": n_images * (gray + 2 * maps),
+        "search": n_pairs * 4 * maps,
+    }
+    per["step"] = sum(per.values())
+    return per
+
+
+def kernel_search_bytes(lay, n_pairs, levels_in_launch):
+    return sum(n_pairs * 4 * 8 * lay.words_per_row[l] * lay.level_height[l] for l in levels_in_launch)
+
+
+def file_sha256(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if still current."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("kernel_source_sha256") != file_sha256(KERNEL_SOURCE):
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(imgs, levels, ref, mp_total, max_threads):
+    import oracle
+
+    threads = max(1, min(max_threads, len(imgs), os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    out = oracle.align_stack(imgs, levels, ref_index=ref, threads=threads)
+    dt = time.perf_counter() - t0
+    return out, {
+        "value": round(mp_total / dt, 3),
+        "unit": "MP/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"one full alignment of the same {len(imgs)}-image stack ({mp_total:.1f} MP), "
+                  f"{dt:.2f} s wall, images then pairs spread over {threads} threads",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="stack7_6000x4000",
+                    choices=["stack7_6000x4000", "pair_4096x3072", "pair_512x384"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the alignment path has no multi-GPU mode "
+              "(stacks are independent; see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be >= 1 and --warmup >= 0")
+
+    import numpy as np
+    import torch
+
+    import paper_2007_06483_amd as mtb
+    import synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    mtb.lib()  # raises if libmtb.so is not built
+    dev = torch.device("cuda:0")
+
+    log(f"generating {args.workload} ...")
+    t0 = time.perf_counter()
+    w = synth.workload(args.workload)
+    (imgs, true_shifts, ref), = w.stacks
+    L = w.levels
+    n = len(imgs)
+    log(f"generated in {time.perf_counter() - t0:.1f} s; uploading")
+    d_imgs = [torch.from_numpy(im).to(dev) for im in imgs]
+    W, H = w.width, w.height
+    mp_total = n * W * H / 1e6
+    lay = mtb.mtb_get_layout(W, H, L)
+    ws = torch.empty(mtb.mtb_stack_workspace_bytes(n, W, H, L), dtype=torch.uint8, device=dev)
+    shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    errs = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def step():
+        mtb.mtb_align_stack(d_imgs, L, ref_index=ref, workspace=ws, shifts=shifts, errs=errs)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # Timed region: K whole-stack alignments; the dominant kernel is bracketed
+    # by HIP events on the launch stream.
+    dominant = "k_pyramid"
+    torch.cuda.synchronize()
+    mtb.mtb_profile_begin(dominant)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = mtb.mtb_profile_end()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"{args.steps} steps: {ms_per_step:.4f} ms/step")
+
+    # Per-kernel breakdown, outside the timed region.
+    nrep = max(3, min(args.steps, 10))
+    mtb.mtb_profile_begin(None)
+    for _ in range(nrep):
+        step()
+    torch.cuda.synchronize()
+    breakdown = mtb.mtb_profile_end()
+
+    gpu_shifts = shifts.cpu().numpy()
+    gpu_errs = errs.cpu().numpy().astype(np.int64)
+
+    algo = algorithmic_bytes(lay, n, n - 1)
+    launches, total_ms = prof[dominant]
+    avg_s = total_ms / launches / 1e3
+    achieved = algo[dominant] / avg_s / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": dominant,
+        "achieved": round(achieved, 1),
+        "peak": PEAK_HBM_GBPS,
+        "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBPS, 4),
+        "traffic": load_traffic(dominant),
+        "avg_launch_us": round(avg_s * 1e6, 2),
+        "algorithmic_bytes_per_launch": algo[dominant],
+    }
+
+    # Paper-comparable end-to-end time: host (pinned) -> device copies included.
+    pinned = [torch.from_numpy(im).pin_memory() for im in imgs]
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for dst, src in zip(d_imgs, pinned):
+            dst.copy_(src, non_blocking=True)
+        step()
+    torch.cuda.synchronize()
+    e2e_ms = (time.perf_counter() - t0) * 1e3 / reps
+
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        a = torch.empty(nb, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes read and written")
+
+    result = {
+        "metric": METRIC,
+        "value": round(mp_total / (ms_per_step / 1e3), 1),
+        "unit": "MP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "images": n,
+            "width": W,
+            "height": H,
+            "levels": L,
+            "ref_index": ref,
+            "exclude_range": 4,
+            "megapixels_per_step": round(mp_total, 3),
+        },
+        "hbm_GBps": round(algo["step"] / (ms_per_step / 1e3) / 1e9, 1),
+        "hbm_model_bytes_per_step": algo["step"],
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: round(v[1] / nrep, 4) for k, v in sorted(breakdown.items())},
+        "e2e_incl_h2d": {"ms_per_step": round(e2e_ms, 3), "MPps": round(mp_total / (e2e_ms / 1e3), 1)},
+    }
+
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle ...")
+        want, cpu = cpu_baseline(imgs, L, ref, mp_total, args.cpu_threads)
+        result["cpu_baseline"] = cpu
+        result["parity_vs_oracle"] = bool(np.array_equal(gpu_shifts, want["shifts"]) and
+                                          np.array_equal(gpu_errs, want["errs"]))
+    result["shifts"] = gpu_shifts.tolist()
+    result["planted_translations"] = [list(t) for t in true_shifts]
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -181,6 +181,29 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
                            size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
                            uint32_t *d_trace, void *stream);
 
+/*
+ * Per-kernel timing for benchmarks.  Between mtb_profile_begin and
+ * mtb_profile_end, every kernel that library calls made from the calling
+ * thread launch is bracketed by two HIP events recorded on its stream; with
+ * kernel_name non-NULL only kernels of that name are (names as listed by
+ * rocprofv3, e.g. "k_pyramid").
+ * mtb_profile_end waits for those events and writes one entry per kernel
+ * name (launch count and summed event-to-event milliseconds) into h_out
+ * (capacity entries), the number of entries into *h_count.
+ * Errors: MTB_ERR_INVALID_ARG (begin while on / end while off / name of
+ *         47 characters or more),
+ *         MTB_ERR_WORKSPACE (more kernel names than capacity; the first
+ *         capacity are still filled), MTB_ERR_DEVICE (an event failed).
+ */
+typedef struct mtb_kernel_time {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} mtb_kernel_time;
+
+mtb_status mtb_profile_begin(const char *kernel_name);
+mtb_status mtb_profile_end(mtb_kernel_time *h_out, int32_t capacity, int32_t *h_count);
+
 #ifdef __cplusplus
 }
 #endif

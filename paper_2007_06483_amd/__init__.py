@@ -35,6 +35,8 @@ __all__ = [
     "mtb_bitmaps",
     "mtb_align_pair",
     "mtb_align_stack",
+    "mtb_profile_begin",
+    "mtb_profile_end",
 ]
 
 MTB_MAX_LEVELS = 16
@@ -74,6 +76,10 @@ class _CLayout(ctypes.Structure):
         ("median_offset", ctypes.c_int64),
         ("bitmaps_bytes", ctypes.c_int64),
     ]
+
+
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
 class Layout:
@@ -129,6 +135,10 @@ def lib():
     L.mtb_align_pair.restype = ctypes.c_int
     L.mtb_align_stack.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, i32, i32, P, sz, P, P, P, P]
     L.mtb_align_stack.restype = ctypes.c_int
+    L.mtb_profile_begin.argtypes = [ctypes.c_char_p]
+    L.mtb_profile_begin.restype = ctypes.c_int
+    L.mtb_profile_end.argtypes = [ctypes.POINTER(_KernelTime), i32, ctypes.POINTER(i32)]
+    L.mtb_profile_end.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -277,3 +287,16 @@ def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int 
                                  _ptr(workspace), workspace.numel(), _ptr(shifts), _ptr(errs),
                                  _ptr(tr), _stream(stream)))
     return {"shifts": shifts, "errs": errs, "trace": tr, "workspace": workspace}
+
+
+def mtb_profile_begin(kernel_name: str | None = None) -> None:
+    """Start timing the library's kernel launches on this thread (optionally one kernel name)."""
+    _check("mtb_profile_begin", lib().mtb_profile_begin(None if kernel_name is None else kernel_name.encode()))
+
+
+def mtb_profile_end(capacity: int = 64) -> dict:
+    """Stop timing; returns {kernel name: (launches, total milliseconds)}."""
+    out = (_KernelTime * capacity)()
+    count = ctypes.c_int32(0)
+    _check("mtb_profile_end", lib().mtb_profile_end(out, capacity, ctypes.byref(count)))
+    return {out[i].name.decode(): (int(out[i].launches), float(out[i].total_ms)) for i in range(count.value)}

@@ -6,7 +6,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmtb.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mtb_api.hip", "mtb_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mtb_api.hip", "mtb_kernels.hip", "mtb_profile.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -125,6 +125,21 @@ struct ZeroArgs {
     int32_t count;
 };
 
+// Brackets one kernel launch with timing events when profiling is on
+// (mtb_profile_begin); otherwise does nothing.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+  private:
+    const char *name_;
+    hipStream_t stream_;
+    void *start_;
+};
+
 // Launch helpers (mtb_kernels.hip).  Each returns the hipError_t of its launches.
 hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);
 hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s);

@@ -661,7 +661,10 @@ hipError_t launch_zero(const ZeroArgs &a, hipStream_t s)
         most = a.words[i] > most ? a.words[i] : most;
     int blocks = (int)((most + 255) / 256);
     blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
-    hipLaunchKernelGGL(k_zero, dim3(blocks, a.count), dim3(256), 0, s, a);
+    {
+        ProfScope prof_("k_zero", s);
+        hipLaunchKernelGGL(k_zero, dim3(blocks, a.count), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -674,7 +677,10 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     per = per < 1 ? 1 : per;
     a.tiles_per_block = (int32_t)per;
     const int blocks = (int)((total + per - 1) / per);
-    hipLaunchKernelGGL(k_pyramid, dim3(blocks), dim3(256), 0, s, a);
+    {
+        ProfScope prof_("k_pyramid", s);
+        hipLaunchKernelGGL(k_pyramid, dim3(blocks), dim3(256), 0, s, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.g.L <= kFused)
         return e;
@@ -684,7 +690,10 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     c.n = a.n;
     c.pad_ = 0;
     c.g = a.g;
-    hipLaunchKernelGGL(k_pyramid_coarse, dim3(a.n), dim3(256), 0, s, c);
+    {
+        ProfScope prof_("k_pyramid_coarse", s);
+        hipLaunchKernelGGL(k_pyramid_coarse, dim3(a.n), dim3(256), 0, s, c);
+    }
     return hipGetLastError();
 }
 
@@ -694,7 +703,10 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
     int64_t blocks = (total + 3) / 4;
     const int64_t cap = (int64_t)cus * 8;
     blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
-    hipLaunchKernelGGL(k_bitmaps, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    {
+        ProfScope prof_("k_bitmaps", s);
+        hipLaunchKernelGGL(k_bitmaps, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -712,7 +724,10 @@ hipError_t launch_search(SearchArgs a, int /*unused*/, hipStream_t s)
         lo = g.L - 1;  // the coarsest level always runs in the coarse kernel
     a.coarse_lo = lo;
     a.rows_per_unit = 4;
-    hipLaunchKernelGGL(k_search_coarse, dim3(a.npairs), dim3(1024), 0, s, a);
+    {
+        ProfScope prof_("k_search_coarse", s);
+        hipLaunchKernelGGL(k_search_coarse, dim3(a.npairs), dim3(1024), 0, s, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -734,7 +749,10 @@ hipError_t launch_search(SearchArgs a, int /*unused*/, hipStream_t s)
         a.rows_per_unit = rows;
         const int units = units_x * ((lv.h + rows * streams - 1) / (rows * streams));
         const int blocks = (units + 3) / 4;
-        hipLaunchKernelGGL(k_search_fine, dim3(blocks, a.npairs), dim3(256), 0, s, a);
+        {
+            ProfScope prof_("k_search_fine", s);
+            hipLaunchKernelGGL(k_search_fine, dim3(blocks, a.npairs), dim3(256), 0, s, a);
+        }
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -744,7 +762,10 @@ hipError_t launch_search(SearchArgs a, int /*unused*/, hipStream_t s)
 
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
+    {
+        ProfScope prof_("k_finalize", s);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,118 @@
+// mtb_profile.hip -- optional per-kernel timing with HIP events.
+//
+// While a thread has profiling switched on (mtb_profile_begin), every kernel
+// the library launches from that thread is bracketed by two events recorded
+// on the launch stream; mtb_profile_end waits for them and reports the total
+// time per kernel name.  Switched off (the default), a launch costs one
+// thread-local flag test.
+
+#include <string.h>
+
+#include <vector>
+
+#include "mtb_internal.h"
+
+namespace mtb {
+namespace {
+
+struct Record {
+    const char *name;
+    hipEvent_t start, stop;
+};
+
+thread_local bool t_enabled = false;
+thread_local char t_filter[48] = {0};  // empty: every kernel
+thread_local std::vector<Record> t_records;
+thread_local hipError_t t_error = hipSuccess;
+
+}  // namespace
+
+ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), stream_(s), start_(nullptr)
+{
+    if (!t_enabled || (t_filter[0] && strcmp(t_filter, name) != 0))
+        return;
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r == hipSuccess)
+        r = hipEventRecord(e, s);
+    if (r != hipSuccess) {
+        t_error = r;
+        if (e)
+            (void)hipEventDestroy(e);
+        return;
+    }
+    start_ = e;
+}
+
+ProfScope::~ProfScope()
+{
+    if (!t_enabled || !start_)
+        return;
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r == hipSuccess)
+        r = hipEventRecord(e, stream_);
+    if (r != hipSuccess) {
+        t_error = r;
+        if (e)
+            (void)hipEventDestroy(e);
+        (void)hipEventDestroy((hipEvent_t)start_);
+        return;
+    }
+    t_records.push_back(Record{name_, (hipEvent_t)start_, e});
+}
+
+}  // namespace mtb
+
+using namespace mtb;
+
+extern "C" {
+
+mtb_status mtb_profile_begin(const char *kernel_name)
+{
+    if (t_enabled || (kernel_name && strlen(kernel_name) >= sizeof(t_filter)))
+        return MTB_ERR_INVALID_ARG;
+    t_filter[0] = 0;
+    if (kernel_name)
+        strcpy(t_filter, kernel_name);
+    t_records.clear();
+    t_error = hipSuccess;
+    t_enabled = true;
+    return MTB_OK;
+}
+
+mtb_status mtb_profile_end(mtb_kernel_time *h_out, int32_t capacity, int32_t *h_count)
+{
+    if (!t_enabled)
+        return MTB_ERR_INVALID_ARG;
+    t_enabled = false;
+    mtb_status status = t_error == hipSuccess ? MTB_OK : MTB_ERR_DEVICE;
+    int32_t count = 0;
+    for (const Record &r : t_records) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+            status = MTB_ERR_DEVICE;
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+        int32_t i = 0;
+        while (i < count && strcmp(h_out[i].name, r.name) != 0)
+            ++i;
+        if (i == count) {
+            if (!h_out || count >= capacity) {
+                status = status == MTB_OK ? MTB_ERR_WORKSPACE : status;
+                continue;
+            }
+            memset(&h_out[i], 0, sizeof(h_out[i]));
+            strncpy(h_out[i].name, r.name, sizeof(h_out[i].name) - 1);
+            ++count;
+        }
+        h_out[i].launches += 1;
+        h_out[i].total_ms += ms;
+    }
+    t_records.clear();
+    if (h_count)
+        *h_count = count;
+    return status;
+}
+
+}  // extern "C"
