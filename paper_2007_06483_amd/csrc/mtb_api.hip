@@ -92,6 +92,13 @@ int current_device_cus()
 
 mtb_status device_status(hipError_t e) { return e == hipSuccess ? MTB_OK : MTB_ERR_DEVICE; }
 
+// Alignment (16, 4 or 1 bytes) that every row start of an image has.
+int row_alignment(const uint8_t *p, int64_t stride)
+{
+    const uintptr_t v = (uintptr_t)p | (uintptr_t)stride;
+    return v % 16 == 0 ? 16 : (v % 4 == 0 ? 4 : 1);
+}
+
 void fill_chunk_starts(const Geometry &g, int64_t *cs)
 {
     cs[0] = 0;
@@ -172,7 +179,7 @@ size_t mtb_pair_workspace_bytes(int32_t levels)
 {
     if (levels < 1 || levels > kMaxLevels)
         return 0;
-    return (size_t)state_stride_words(levels) * 4;
+    return (size_t)(state_stride_words(levels) + kAlign / 4) * 4;  // state, then the done counter
 }
 
 size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t levels)
@@ -180,8 +187,9 @@ size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32
     Geometry g;
     if (n < 1 || n > kMaxStack || !make_geometry(width, height, levels, &g))
         return 0;
+    // pyramids, bitmaps, search state, done counter, plus slack to align the start
     return (size_t)(n * (g.pyramid_bytes + g.bitmaps_bytes) + (n - 1) * state_stride_words(levels) * 4 +
-                    kAlign);
+                    2 * kAlign);
 }
 
 mtb_status mtb_build_pyramid(const uint8_t *d_rgb, int32_t width, int32_t height,
@@ -216,9 +224,7 @@ mtb_status mtb_build_pyramid(const uint8_t *d_rgb, int32_t width, int32_t height
     a.pyr[0] = pyr;
     a.stride = row_stride;
     a.n = 1;
-    a.tiles_x = (width + kTile - 1) / kTile;
-    a.tiles_y = (height + kTile - 1) / kTile;
-    a.aligned = ((uintptr_t)d_rgb % 4 == 0) && (row_stride % 4 == 0);
+    a.align = row_alignment(d_rgb, row_stride);
     a.g = g;
     return device_status(launch_pyramid(a, cus, s));
 }
@@ -267,7 +273,7 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
     ZeroArgs z;
     memset(&z, 0, sizeof(z));
     z.ptr[0] = state;
-    z.words[0] = pair_state_words(levels);
+    z.words[0] = state_stride_words(levels) + 1;  // counters, bases and the done counter
     z.count = 1;
     if (launch_zero(z, s) != hipSuccess)
         return MTB_ERR_DEVICE;
@@ -277,25 +283,17 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
     a.ref[0] = (const uint8_t *)d_bm_ref;
     a.mov[0] = (const uint8_t *)d_bm_mov;
     a.state = state;
+    a.done = state + state_stride_words(levels);
     a.state_stride = state_stride_words(levels);
     a.npairs = 1;
+    a.out.pair_image[0] = 0;
+    a.out.n_out = 1;
+    a.out.shifts = d_shift;
+    a.out.errs = d_err;
+    a.out.trace = d_trace;
+    a.out.level_shifts = d_level_shifts;
     a.g = g;
-    if (launch_search(a, 0, s) != hipSuccess)
-        return MTB_ERR_DEVICE;
-
-    FinalizeArgs f;
-    memset(&f, 0, sizeof(f));
-    f.state = state;
-    f.state_stride = a.state_stride;
-    f.npairs = 1;
-    f.L = levels;
-    f.pair_image[0] = 0;
-    f.n_out = 1;
-    f.shifts = d_shift;
-    f.errs = d_err;
-    f.trace = d_trace;
-    f.level_shifts = d_level_shifts;
-    return device_status(launch_finalize(f, s));
+    return device_status(launch_search(a, s));
 }
 
 mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
@@ -313,11 +311,12 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
     const int ref = ref_index < 0 ? n / 2 : ref_index;
     if (ref >= n)
         return MTB_ERR_INVALID_ARG;
-    bool aligned = row_stride % 4 == 0;
+    int align = 16;
     for (int i = 0; i < n; ++i) {
         if (!h_d_rgb[i])
             return MTB_ERR_INVALID_ARG;
-        aligned = aligned && ((uintptr_t)h_d_rgb[i] % 4 == 0);
+        const int ai = row_alignment(h_d_rgb[i], row_stride);
+        align = ai < align ? ai : align;
     }
     if (workspace_bytes < mtb_stack_workspace_bytes(n, width, height, levels))
         return MTB_ERR_WORKSPACE;
@@ -333,6 +332,7 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
     uint32_t *state = (uint32_t *)(bm0 + n * g.bitmaps_bytes);
     const int64_t sstride = state_stride_words(levels);
     const int npairs = n - 1;
+    uint32_t *done = state + sstride * npairs;
 
     ZeroArgs z;
     memset(&z, 0, sizeof(z));
@@ -340,11 +340,19 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
         z.ptr[i] = (uint32_t *)(pyr0 + i * g.pyramid_bytes + g.hist_off);
         z.words[i] = (int64_t)levels * 256;
     }
-    z.count = n;
-    if (npairs > 0) {
-        z.ptr[n] = state;
-        z.words[n] = sstride * npairs;
-        z.count = n + 1;
+    z.ptr[n] = state;
+    z.words[n] = sstride * npairs + 1;  // every pair's counters and bases, then the done counter
+    z.count = n + 1;
+    if (npairs == 0) {
+        // A lone image is its own reference: its outputs are zero and there is nothing to search.
+        z.ptr[z.count] = (uint32_t *)d_shifts;
+        z.words[z.count++] = 2;
+        z.ptr[z.count] = d_errs;
+        z.words[z.count++] = 1;
+        if (d_trace) {
+            z.ptr[z.count] = d_trace;
+            z.words[z.count++] = 9 * (int64_t)levels;
+        }
     }
     if (launch_zero(z, s) != hipSuccess)
         return MTB_ERR_DEVICE;
@@ -357,9 +365,7 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
     }
     pa.stride = row_stride;
     pa.n = n;
-    pa.tiles_x = (width + kTile - 1) / kTile;
-    pa.tiles_y = (height + kTile - 1) / kTile;
-    pa.aligned = aligned;
+    pa.align = align;
     pa.g = g;
     if (launch_pyramid(pa, cus, s) != hipSuccess)
         return MTB_ERR_DEVICE;
@@ -376,38 +382,31 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
     fill_chunk_starts(g, ba.chunk_start);
     if (launch_bitmaps(ba, cus, s) != hipSuccess)
         return MTB_ERR_DEVICE;
+    if (npairs == 0)
+        return MTB_OK;
 
-    FinalizeArgs f;
-    memset(&f, 0, sizeof(f));
-    if (npairs > 0) {
-        SearchArgs sa;
-        memset(&sa, 0, sizeof(sa));
-        int p = 0;
-        for (int i = 0; i < n; ++i) {
-            if (i == ref)
-                continue;
-            sa.ref[p] = bm0 + ref * g.bitmaps_bytes;
-            sa.mov[p] = bm0 + i * g.bitmaps_bytes;
-            f.pair_image[p] = i;
-            ++p;
-        }
-        sa.state = state;
-        sa.state_stride = sstride;
-        sa.npairs = npairs;
-        sa.g = g;
-        if (launch_search(sa, 0, s) != hipSuccess)
-            return MTB_ERR_DEVICE;
+    SearchArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    int p = 0;
+    for (int i = 0; i < n; ++i) {
+        if (i == ref)
+            continue;
+        sa.ref[p] = bm0 + ref * g.bitmaps_bytes;
+        sa.mov[p] = bm0 + i * g.bitmaps_bytes;
+        sa.out.pair_image[p] = i;
+        ++p;
     }
-    f.state = state;
-    f.state_stride = sstride;
-    f.npairs = npairs;
-    f.L = levels;
-    f.n_out = n;
-    f.shifts = d_shifts;
-    f.errs = d_errs;
-    f.trace = d_trace;
-    f.level_shifts = nullptr;
-    return device_status(launch_finalize(f, s));
+    sa.state = state;
+    sa.done = done;
+    sa.state_stride = sstride;
+    sa.npairs = npairs;
+    sa.out.n_out = n;
+    sa.out.shifts = d_shifts;
+    sa.out.errs = d_errs;
+    sa.out.trace = d_trace;
+    sa.out.level_shifts = nullptr;
+    sa.g = g;
+    return device_status(launch_search(sa, s));
 }
 
 }  // extern "C"

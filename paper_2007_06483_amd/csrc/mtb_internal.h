@@ -13,9 +13,11 @@ constexpr int kMaxLevels = MTB_MAX_LEVELS;
 constexpr int kMaxStack = MTB_MAX_STACK;
 constexpr int kAlign = 256;
 
-// Pass 1 fuses this many pyramid levels per 64x64 tile (64 = 2^(kFused-1)).
+// Pass 1 fuses this many pyramid levels per workgroup tile; the tile is
+// kTileH = 2^(kFused-1) rows by kTileW columns of level 0.
 constexpr int kFused = 7;
-constexpr int kTile = 64;
+constexpr int kTileH = 64;
+constexpr int kTileW = 256;
 
 // Search counters are spread over this many copies per (pair, level) so that
 // concurrent workgroups do not all add into the same nine words.
@@ -58,7 +60,7 @@ struct PyramidArgs {
     int32_t n;               // images
     int32_t tiles_x, tiles_y;
     int32_t tiles_per_block; // contiguous tiles handled by one workgroup
-    int32_t aligned;         // 1 if every RGB row start is 4-byte aligned
+    int32_t align;           // 16, 4 or 1: alignment every RGB row start is known to have
     int32_t pad_;
     Geometry g;
 };
@@ -74,7 +76,7 @@ struct CoarsePyramidArgs {
 
 // The bitmaps pass walks each level as a flat run of 64-pixel words, in
 // chunks of kChunkWords words (kChunkWords * 64 gray bytes) per wavefront.
-constexpr int kChunkWords = 16;
+constexpr int kChunkWords = 32;
 
 struct BitmapArgs {
     const uint8_t *pyr[kMaxStack];
@@ -91,25 +93,9 @@ struct BitmapArgs {
 // base int32[L][2] (the centre of each level's nine candidates).
 inline int64_t pair_state_words(int32_t L) { return (int64_t)L * kCounterWords + 2 * L; }
 
-struct SearchArgs {
-    const uint8_t *ref[kMaxStack];   // bitmaps buffer of each pair's reference
-    const uint8_t *mov[kMaxStack];   // bitmaps buffer of each pair's moving image
-    uint32_t *state;                 // pair p's state at state + p * state_stride
-    int64_t state_stride;            // uint32 words
-    int32_t npairs;
-    int32_t level;                   // fine kernel: the level searched
-    int32_t coarse_lo;               // coarse kernel: lowest level it searches
-    int32_t rows_per_unit;           // rows per wavefront work unit
-    int32_t units_x;                 // 64-dword column strips per row (current level)
-    int32_t units_per_pair;          // work units per pair (current level)
-    Geometry g;
-};
-
-struct FinalizeArgs {
-    const uint32_t *state;
-    int64_t state_stride;
-    int32_t npairs;
-    int32_t L;
+// Where the search writes its results; the last workgroup of the launch
+// that searches level 0 fills them in.
+struct SearchOutputs {
     int32_t pair_image[kMaxStack];   // output row of each pair (stack index)
     int32_t n_out;                   // rows of the outputs
     int32_t pad_;
@@ -117,6 +103,20 @@ struct FinalizeArgs {
     uint32_t *errs;                  // [n_out]
     uint32_t *trace;                 // NULL or [n_out][L][9]
     int32_t *level_shifts;           // NULL or [n_out][L][2]
+};
+
+struct SearchArgs {
+    const uint8_t *ref[kMaxStack];   // bitmaps buffer of each pair's reference
+    const uint8_t *mov[kMaxStack];   // bitmaps buffer of each pair's moving image
+    uint32_t *state;                 // pair p's state at state + p * state_stride
+    uint32_t *done;                  // workgroups finished in the level-0 launch
+    int64_t state_stride;            // uint32 words
+    int32_t npairs;
+    int32_t level;                   // fine kernel: the level searched
+    int32_t coarse_lo;               // coarse kernel: lowest level it searches
+    int32_t rows_per_stream;         // rows per lane in one work unit
+    SearchOutputs out;
+    Geometry g;
 };
 
 struct ZeroArgs {
@@ -144,7 +144,8 @@ class ProfScope {
 hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);
 hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s);
 hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s);
-hipError_t launch_search(SearchArgs a, int coarse_lo, hipStream_t s);
-hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t s);
+// Searches every level of every pair and writes a.out; a.state and *a.done
+// must be zero.
+hipError_t launch_search(SearchArgs a, hipStream_t s);
 
 }  // namespace mtb
