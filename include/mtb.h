@@ -66,14 +66,15 @@ typedef enum mtb_status {
  *   level l threshold bitmap T and exclusion bitmap E: each level_height[l]
  *     rows of words_per_row[l] uint64 words at tb_offset[l] / eb_offset[l];
  *     pixel x of row y is bit (x % 64) of word (x / 64) of the row (least
- *     significant bit first); bits past level_width[l] are 0;
+ *     significant bit first); bits past level_width[l] are 0 (rows are
+ *     padded to a multiple of 128 pixels);
  *   medians: int32 median[levels] at median_offset.
  */
 typedef struct mtb_layout {
     int32_t width, height, levels;
     int32_t level_width[MTB_MAX_LEVELS];
     int32_t level_height[MTB_MAX_LEVELS];
-    int32_t words_per_row[MTB_MAX_LEVELS]; /* ceil(level_width / 64) */
+    int32_t words_per_row[MTB_MAX_LEVELS]; /* 2 * ceil(level_width / 128) */
     int64_t gray_offset[MTB_MAX_LEVELS];
     int64_t gray_pitch[MTB_MAX_LEVELS]; /* 64 * words_per_row */
     int64_t hist_offset;

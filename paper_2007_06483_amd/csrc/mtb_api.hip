@@ -34,7 +34,8 @@ bool make_geometry(int32_t W, int32_t H, int32_t L, Geometry *g)
         LevelGeom &lv = g->lv[l];
         lv.w = W >> l;
         lv.h = H >> l;
-        lv.wpr = (lv.w + 63) / 64;
+        // Rows padded to 128 pixels: gray rows start on 128-byte lines.
+        lv.wpr = 2 * ((lv.w + 127) / 128);
         lv.gray_pitch = 64 * (int64_t)lv.wpr;
         lv.gray_off = off;
         off = align_up(off + lv.gray_pitch * lv.h, kAlign);
@@ -273,7 +274,7 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
     ZeroArgs z;
     memset(&z, 0, sizeof(z));
     z.ptr[0] = state;
-    z.words[0] = state_stride_words(levels) + 1;  // counters, bases and the done counter
+    z.words[0] = state_stride_words(levels) + 2;  // counters, bases, surfaces, ticket counters
     z.count = 1;
     if (launch_zero(z, s) != hipSuccess)
         return MTB_ERR_DEVICE;
@@ -341,7 +342,7 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
         z.words[i] = (int64_t)levels * 256;
     }
     z.ptr[n] = state;
-    z.words[n] = sstride * npairs + 1;  // every pair's counters and bases, then the done counter
+    z.words[n] = sstride * npairs + 2;  // every pair's search state, then the ticket counters
     z.count = n + 1;
     if (npairs == 0) {
         // A lone image is its own reference: its outputs are zero and there is nothing to search.

@@ -30,10 +30,10 @@ inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 // Geometry of one pyramid level, with offsets into the per-image buffers.
 struct LevelGeom {
     int32_t w, h;         // level size in pixels
-    int32_t wpr;          // uint64 words per bitmap row = ceil(w / 64)
+    int32_t wpr;          // uint64 words per bitmap row = 2 * ceil(w / 128)
     int32_t pad_;
     int64_t gray_off;     // bytes, pyramid buffer
-    int64_t gray_pitch;   // bytes = 64 * wpr
+    int64_t gray_pitch;   // bytes = 64 * wpr, a multiple of 128
     int64_t tb_off;       // bytes, bitmaps buffer
     int64_t eb_off;       // bytes, bitmaps buffer
 };
@@ -89,9 +89,18 @@ struct BitmapArgs {
 
 // ------------------------------------------------------------------ search
 
+// The coarsest levels (at most kCoarseLevels) are searched exhaustively over
+// every shift the coarse-to-fine search could reach there: radius 2^(i+1) - 1
+// at the i-th coarsest level.  Their error surfaces take kSurfWords words.
+constexpr int kCoarseLevels = 3;
+constexpr int kSurfWords = 3 * 3 + 7 * 7 + 15 * 15;
+
 // Per pair the search state is: counters uint32[L][kCounterWords], then
-// base int32[L][2] (the centre of each level's nine candidates).
-inline int64_t pair_state_words(int32_t L) { return (int64_t)L * kCounterWords + 2 * L; }
+// base int32[L][2] (the centre of each level's nine candidates), then the
+// coarse error surfaces uint32[kSurfWords].  After every pair's state come two
+// ticket counters: workgroups finished in the coarse launch and in the
+// level-0 launch.
+inline int64_t pair_state_words(int32_t L) { return (int64_t)L * kCounterWords + 2 * L + kSurfWords; }
 
 // Where the search writes its results; the last workgroup of the launch
 // that searches level 0 fills them in.
@@ -109,11 +118,11 @@ struct SearchArgs {
     const uint8_t *ref[kMaxStack];   // bitmaps buffer of each pair's reference
     const uint8_t *mov[kMaxStack];   // bitmaps buffer of each pair's moving image
     uint32_t *state;                 // pair p's state at state + p * state_stride
-    uint32_t *done;                  // workgroups finished in the level-0 launch
+    uint32_t *done;                  // [0] coarse-launch tickets, [1] level-0 launch tickets
     int64_t state_stride;            // uint32 words
     int32_t npairs;
     int32_t level;                   // fine kernel: the level searched
-    int32_t coarse_lo;               // coarse kernel: lowest level it searches
+    int32_t coarse_n;                // levels L-1 .. L-coarse_n searched exhaustively
     int32_t rows_per_stream;         // rows per lane in one work unit
     SearchOutputs out;
     Geometry g;

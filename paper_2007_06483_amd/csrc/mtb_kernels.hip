@@ -59,18 +59,44 @@ __device__ __forceinline__ uint32_t pack4(const uint32_t *v)
     return v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
 }
 
+// Level-0 histogram privatisation: kH0Copies copies per wave, lane l adding
+// into copy (l % kH0Copies); copies kHStride (odd) words apart, so that equal
+// values from lanes of different copies fall into different LDS banks.
+constexpr int kH0Copies = 4;
+constexpr int kHStride = 257;
+
+// Loads one lane's 4 rows x 48 bytes (16 pixels) of RGB with 16-byte loads;
+// rows at or below H read as zero.
+__device__ __forceinline__ void load_rgb16(const uint8_t *rgb, int64_t stride, int x0, int y0, int H,
+                                           uint4 (&q)[4][3])
+{
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        if (y0 + rr < H) {
+            const uint4 *p = (const uint4 *)(rgb + (int64_t)(y0 + rr) * stride + 3 * (int64_t)x0);
+            q[rr][0] = p[0];
+            q[rr][1] = p[1];
+            q[rr][2] = p[2];
+        } else {
+            q[rr][0] = q[rr][1] = q[rr][2] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+}
+
 // Workgroup tile: kTileH = 64 rows x kTileW = 256 columns of level 0.  Wave w
 // owns rows 16w .. 16w+15; lane (bx = lane & 15, by = lane >> 4) owns the
 // 4-row x 16-column block at (X0 + 16 bx, Y0 + 16 w + 4 by).  Levels 1 and 2
 // stay inside the lane, levels 3 and 4 combine lanes of the wave with
 // shuffles, levels 5 and 6 combine the four waves through LDS.  Each lane
-// reads 4 x 48 bytes of RGB per tile; a row of 16 lanes covers 768
-// contiguous bytes.
+// reads 4 x 48 bytes of RGB per tile (a row of 16 lanes covers 768
+// contiguous bytes), and with 16-byte aligned rows the next tile's RGB is
+// loaded while the current one is processed.
 __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
 {
-    __shared__ uint32_t hist01[4][2][256];        // per wave, levels 0 and 1
-    __shared__ uint32_t histc[kFused - 2][256];   // levels 2 .. 6, whole workgroup
-    __shared__ uint32_t lvl4[2][4][16];           // level-4 pixels of a tile, by tile parity
+    __shared__ uint32_t hist0[4 * kH0Copies * kHStride];  // level 0, per wave and lane group
+    __shared__ uint32_t hist1[4][256];                    // level 1, per wave
+    __shared__ uint32_t histc[kFused - 2][256];           // levels 2 .. 6, whole workgroup
+    __shared__ uint32_t lvl4[2][4][16];                   // level-4 pixels of a tile, by tile parity
 
     const int tid = threadIdx.x;
     const int wave = wave_id();
@@ -78,9 +104,12 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     const int bx = lane & 15, by = lane >> 4;
     const Geometry &g = a.g;
     const int fused = g.L < kFused ? g.L : kFused;
+    uint32_t *h0 = hist0 + (wave * kH0Copies + (lane % kH0Copies)) * kHStride;
 
-    for (int i = tid; i < 4 * 2 * 256; i += 256)
-        (&hist01[0][0][0])[i] = 0u;
+    for (int i = tid; i < 4 * kH0Copies * kHStride; i += 256)
+        hist0[i] = 0u;
+    for (int i = tid; i < 4 * 256; i += 256)
+        (&hist1[0][0])[i] = 0u;
     for (int i = tid; i < (kFused - 2) * 256; i += 256)
         (&histc[0][0])[i] = 0u;
     __syncthreads();
@@ -94,10 +123,15 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
         __syncthreads();
         uint32_t *gh = (uint32_t *)(a.pyr[img] + g.hist_off);
         for (int l = 0; l < fused; ++l) {
-            uint32_t s;
-            if (l < 2) {
-                s = hist01[0][l][tid] + hist01[1][l][tid] + hist01[2][l][tid] + hist01[3][l][tid];
-                hist01[0][l][tid] = hist01[1][l][tid] = hist01[2][l][tid] = hist01[3][l][tid] = 0u;
+            uint32_t s = 0;
+            if (l == 0) {
+                for (int c = 0; c < 4 * kH0Copies; ++c) {
+                    s += hist0[c * kHStride + tid];
+                    hist0[c * kHStride + tid] = 0u;
+                }
+            } else if (l == 1) {
+                s = hist1[0][tid] + hist1[1][tid] + hist1[2][tid] + hist1[3][tid];
+                hist1[0][tid] = hist1[1][tid] = hist1[2][tid] = hist1[3][tid] = 0u;
             } else {
                 s = histc[l - 2][tid];
                 histc[l - 2][tid] = 0u;
@@ -108,38 +142,42 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
         __syncthreads();
     };
 
+    // Tile t -> image and level-0 origin of this lane's block.
+    auto locate = [&](int64_t t, int &img, int &X0, int &Y0) {
+        img = (int)(t / per_image);
+        const int64_t r = t - (int64_t)img * per_image;
+        X0 = (int)(r % a.tiles_x) * kTileW;
+        Y0 = (int)(r / a.tiles_x) * kTileH;
+    };
+
+    const bool fast16 = a.align == 16;
+    uint4 q[4][3];
+    if (fast16 && t0 < t1) {
+        int img, X0, Y0;
+        locate(t0, img, X0, Y0);
+        const int x0 = X0 + 16 * bx;
+        if (x0 + 15 < g.W)
+            load_rgb16(a.rgb[img], a.stride, x0, Y0 + 16 * wave + 4 * by, g.H, q);
+    }
+
     int cur = -1;
     int parity = 0;
     for (int64_t t = t0; t < t1; ++t) {
-        const int img = (int)(t / per_image);
+        int img, X0, Y0;
+        locate(t, img, X0, Y0);
         if (img != cur) {
             if (cur >= 0)
                 flush(cur);
             cur = img;
         }
-        const int64_t r = t - (int64_t)img * per_image;
-        const int tx = (int)(r % a.tiles_x), ty = (int)(r / a.tiles_x);
-        const int X0 = tx * kTileW, Y0 = ty * kTileH;
         const int x0 = X0 + 16 * bx, y0 = Y0 + 16 * wave + 4 * by;
         const uint8_t *rgb = a.rgb[img];
         uint8_t *pyr = a.pyr[img];
         const bool full = x0 + 15 < g.W;
 
-        // ---- level 0: gray of the 4x16 block; all loads issued before any use
+        // ---- level 0: gray of the 4x16 block
         uint32_t gv[4][16];
-        if (a.align == 16 && full) {
-            uint4 q[4][3];
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                if (y0 + rr < g.H) {
-                    const uint4 *p = (const uint4 *)(rgb + (int64_t)(y0 + rr) * a.stride + 3 * (int64_t)x0);
-                    q[rr][0] = p[0];
-                    q[rr][1] = p[1];
-                    q[rr][2] = p[2];
-                } else {
-                    q[rr][0] = q[rr][1] = q[rr][2] = make_uint4(0u, 0u, 0u, 0u);
-                }
-            }
+        if (fast16 && full) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const uint32_t d[12] = {q[rr][0].x, q[rr][0].y, q[rr][0].z, q[rr][0].w,
@@ -174,6 +212,14 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
                                     : 0u;
             }
         }
+        // ---- prefetch the next tile's RGB while this one is processed
+        if (fast16 && t + 1 < t1) {
+            int img2, X2, Y2;
+            locate(t + 1, img2, X2, Y2);
+            const int x2 = X2 + 16 * bx;
+            if (x2 + 15 < g.W)
+                load_rgb16(a.rgb[img2], a.stride, x2, Y2 + 16 * wave + 4 * by, g.H, q);
+        }
         {
             const LevelGeom &lv = g.lv[0];
 #pragma unroll
@@ -186,12 +232,12 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
                     if (full) {
 #pragma unroll
                         for (int c = 0; c < 16; ++c)
-                            atomicAdd(&hist01[wave][0][gv[rr][c]], 1u);
+                            atomicAdd(&h0[gv[rr][c]], 1u);
                     } else {
 #pragma unroll
                         for (int c = 0; c < 16; ++c)
                             if (x0 + c < g.W)
-                                atomicAdd(&hist01[wave][0][gv[rr][c]], 1u);
+                                atomicAdd(&h0[gv[rr][c]], 1u);
                     }
                 }
             }
@@ -215,7 +261,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
 #pragma unroll
                     for (int j = 0; j < 8; ++j)
                         if (x1 + j < l1.w)
-                            atomicAdd(&hist01[wave][1][u1[i][j]], 1u);
+                            atomicAdd(&hist1[wave][u1[i][j]], 1u);
                 }
             }
             if (fused > 2) {
@@ -268,11 +314,11 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
                             if (by == 0)
                                 lvl4[parity][wave][bx] = u4;
                             __syncthreads();
-                            const uint32_t(*q)[16] = lvl4[parity];
+                            const uint32_t(*qq)[16] = lvl4[parity];
                             if (tid < 16) {
                                 const int i5 = tid >> 3, j5 = tid & 7;
-                                const uint32_t u5 = (q[2 * i5][2 * j5] + q[2 * i5][2 * j5 + 1] +
-                                                     q[2 * i5 + 1][2 * j5] + q[2 * i5 + 1][2 * j5 + 1]) >> 2;
+                                const uint32_t u5 = (qq[2 * i5][2 * j5] + qq[2 * i5][2 * j5 + 1] +
+                                                     qq[2 * i5 + 1][2 * j5] + qq[2 * i5 + 1][2 * j5 + 1]) >> 2;
                                 const LevelGeom &l5 = g.lv[5];
                                 const int x5 = (X0 >> 5) + j5, y5 = (Y0 >> 5) + i5;
                                 if (y5 < l5.h && x5 < l5.w) {
@@ -286,8 +332,8 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
                                 for (int i = 0; i < 2; ++i)
 #pragma unroll
                                     for (int j = 2 * j6; j < 2 * j6 + 2; ++j)
-                                        s6 += (q[2 * i][2 * j] + q[2 * i][2 * j + 1] + q[2 * i + 1][2 * j] +
-                                               q[2 * i + 1][2 * j + 1]) >> 2;
+                                        s6 += (qq[2 * i][2 * j] + qq[2 * i][2 * j + 1] + qq[2 * i + 1][2 * j] +
+                                               qq[2 * i + 1][2 * j + 1]) >> 2;
                                 const uint32_t u6 = s6 >> 2;
                                 const LevelGeom &l6 = g.lv[6];
                                 const int x6 = (X0 >> 6) + j6, y6 = Y0 >> 6;
@@ -367,9 +413,16 @@ __device__ uint32_t wave_median(const uint32_t *hist, uint32_t npix)
     return __shfl(v, f < 0 ? 0 : f);
 }
 
-// Moves a wave-uniform 32-bit value into one lane of a vector register.
-#define MTB_WRITELANE(dst, val, lane_imm) \
-    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(dst) : "s"(val), "i"(lane_imm))
+// Writes the two 64-bit ballots t and e (as scalar halves) into lane j and
+// lane j + 32 of the word held in (lo, hi).  v_writelane reads its scalar
+// operands early, so the ballots (just written by VALU compares) are given
+// five wait states first.
+#define MTB_WRITELANES(lo, hi, t, e, j)                                                      \
+    asm volatile("s_nop 4\n\tv_writelane_b32 %0, %2, %6\n\tv_writelane_b32 %1, %3, %6\n\t"   \
+                 "v_writelane_b32 %0, %4, %7\n\tv_writelane_b32 %1, %5, %7"                    \
+                 : "+v"(lo), "+v"(hi)                                                        \
+                 : "s"((uint32_t)(t)), "s"((uint32_t)((t) >> 32)), "s"((uint32_t)(e)),         \
+                   "s"((uint32_t)((e) >> 32)), "i"(j), "i"((j) + 32))
 
 struct ChunkPos {
     int img, level, w0, cnt;
@@ -451,10 +504,6 @@ __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
             load_chunk(a, p, lane, v0, v1);
         }
 
-        // Bits past the level width are zero: only the last word of a row is partial.
-        const int tail = lv.w & 63;
-        const uint64_t last_mask = tail ? ((1ull << tail) - 1ull) : ~0ull;
-        int k = cp.w0 % lv.wpr;
         uint32_t out_lo = 0, out_hi = 0;
         const uint32_t ebias = X - m;
         uint32_t gvs[kChunkWords];  // all reads issued before the first use
@@ -464,19 +513,18 @@ __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
 #pragma unroll
         for (int j = 0; j < kChunkWords; ++j) {
             if (j < cp.cnt) {
-                const uint32_t gv = gvs[j];
-                const uint64_t vm = k == lv.wpr - 1 ? last_mask : ~0ull;
-                const uint64_t tw = ballot(gv > m) & vm;
-                const uint64_t ew = ballot(gv + ebias > 2u * X) & vm;
-                const uint32_t tlo = (uint32_t)tw, thi = (uint32_t)(tw >> 32);
-                const uint32_t elo = (uint32_t)ew, ehi = (uint32_t)(ew >> 32);
-                MTB_WRITELANE(out_lo, tlo, j);
-                MTB_WRITELANE(out_hi, thi, j);
-                MTB_WRITELANE(out_lo, elo, j + 32);
-                MTB_WRITELANE(out_hi, ehi, j + 32);
-                if (++k == lv.wpr)
-                    k = 0;
+                const uint64_t tw = ballot(gvs[j] > m);
+                const uint64_t ew = ballot(gvs[j] + ebias > 2u * X);
+                MTB_WRITELANES(out_lo, out_hi, tw, ew, j);
             }
+        }
+        // Bits past the level width are zero: lane i holds word w0 + i % 32, whose
+        // pixels start at column 64 * ((w0 + i % 32) mod wpr).
+        const int nbits = lv.w - 64 * ((cp.w0 + (lane & 31)) % lv.wpr);
+        if (nbits < 64) {
+            const uint64_t keep = nbits <= 0 ? 0ull : ((1ull << nbits) - 1ull);
+            out_lo &= (uint32_t)keep;
+            out_hi &= (uint32_t)(keep >> 32);
         }
         const uint64_t word = ((uint64_t)out_hi << 32) | out_lo;
         if (lane < 32) {
@@ -626,17 +674,45 @@ __host__ __device__ __forceinline__ UnitPlan plan_level(const LevelGeom &lv, int
     return p;
 }
 
-__device__ __forceinline__ uint32_t load_counter(const uint32_t *p)
+// Loads and stores of words that several workgroups (on different XCDs) exchange
+// within one launch: agent-scope atomics, performed at the coherence point.
+__device__ __forceinline__ uint32_t load_shared(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Run by the last workgroup to finish level 0: walks every pair's counters
-// from the coarsest level down and writes the outputs.  Rows of images that
-// are not the moving image of a pair (the reference) are zero.
+__device__ __forceinline__ void store_shared(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t *pair_state(const SearchArgs &a, int p)
+{
+    return a.state + (int64_t)p * a.state_stride;
+}
+
+__device__ __forceinline__ int32_t *pair_bases(const SearchArgs &a, int p)
+{
+    return (int32_t *)(pair_state(a, p) + (int64_t)a.g.L * kCounterWords);
+}
+
+__device__ __forceinline__ uint32_t *pair_surface(const SearchArgs &a, int p)
+{
+    return pair_state(a, p) + (int64_t)a.g.L * kCounterWords + 2 * a.g.L;
+}
+
+// Radius of the exhaustive window at the i-th coarsest level, and where its
+// (2R+1)^2 surface starts.
+__host__ __device__ __forceinline__ int coarse_radius(int i) { return (2 << i) - 1; }
+__device__ __forceinline__ int coarse_surface_offset(int i) { return i == 0 ? 0 : (i == 1 ? 9 : 58); }
+
+// Writes the outputs from every pair's per-level counters (the sum of their
+// kCopies copies), walking from the coarsest level down.  Rows of images that
+// are not the moving image of a pair (the reference) are zero.  Run by one
+// workgroup once every counter is final.
 __device__ void finalize(const SearchArgs &a)
 {
-    __shared__ uint32_t tot[kMaxStack][9];
+    __shared__ uint32_t tot[kMaxStack * kMaxLevels * 9];
     const int L = a.g.L;
     const SearchOutputs &o = a.out;
     for (int r = threadIdx.x; r < o.n_out; r += blockDim.x) {
@@ -650,29 +726,30 @@ __device__ void finalize(const SearchArgs &a)
             for (int i = 0; i < 2 * L; ++i)
                 o.level_shifts[(int64_t)r * 2 * L + i] = 0;
     }
-    __syncthreads();
-    int bx = 0, by = 0, sx = 0, sy = 0;
-    uint32_t err = 0;
-    for (int l = L - 1; l >= 0; --l) {
-        for (int i = threadIdx.x; i < a.npairs * 9; i += blockDim.x) {
-            const int p = i / 9, c = i % 9;
-            const uint32_t *cnt = a.state + (int64_t)p * a.state_stride + l * kCounterWords + c;
-            uint32_t s = 0;
+    // All counters of all pairs and levels at once: item (p, l, c).
+    for (int i = threadIdx.x; i < a.npairs * L * 9; i += blockDim.x) {
+        const int p = i / (L * 9), l = (i / 9) % L, c = i % 9;
+        const uint32_t *cnt = pair_state(a, p) + l * kCounterWords + c;
+        uint32_t s = 0;
 #pragma unroll
-            for (int k = 0; k < kCopies; ++k)
-                s += load_counter(cnt + 9 * k);
-            tot[p][c] = s;
-        }
-        __syncthreads();
-        if ((int)threadIdx.x < a.npairs) {
-            const int p = threadIdx.x, r = o.pair_image[p];
-            const int best = argmin9(tot[p]);
+        for (int k = 0; k < kCopies; ++k)
+            s += load_shared(cnt + 9 * k);
+        tot[i] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < a.npairs) {
+        const int p = threadIdx.x, r = o.pair_image[p];
+        int bx = 0, by = 0, sx = 0, sy = 0;
+        uint32_t err = 0;
+        for (int l = L - 1; l >= 0; --l) {
+            const uint32_t *c = tot + (p * L + l) * 9;
+            const int best = argmin9(c);
             sx = bx + best % 3 - 1;
             sy = by + best / 3 - 1;
-            err = tot[p][best];
+            err = c[best];
             if (o.trace)
                 for (int i = 0; i < 9; ++i)
-                    o.trace[((int64_t)r * L + l) * 9 + i] = tot[p][i];
+                    o.trace[((int64_t)r * L + l) * 9 + i] = c[i];
             if (o.level_shifts) {
                 o.level_shifts[((int64_t)r * L + l) * 2] = sx;
                 o.level_shifts[((int64_t)r * L + l) * 2 + 1] = sy;
@@ -680,90 +757,161 @@ __device__ void finalize(const SearchArgs &a)
             bx = 2 * sx;
             by = 2 * sy;
         }
-        __syncthreads();
-    }
-    if ((int)threadIdx.x < a.npairs) {
-        const int r = o.pair_image[threadIdx.x];
         o.shifts[2 * r] = sx;
         o.shifts[2 * r + 1] = sy;
         o.errs[r] = err;
     }
 }
 
-// After this workgroup's counter updates: if it is the last workgroup of a
-// launch that searched level 0, write the outputs.
+// Takes a ticket from *done once this workgroup's shared writes have
+// completed; true in the workgroup that takes the last ticket of the launch.
 //
 // Ordering without device-wide fences (which on gfx950 write back the whole
-// L2): the counters are only ever updated with agent-scope atomics and read
-// back with agent-scope atomic loads, both performed at the coherence point.
-// The workgroup barrier waits until this workgroup's counter atomics have
-// completed before thread 0 takes its ticket, and the ticket counter is a
-// single agent-scope atomic, so the workgroup that draws the last ticket
-// observes every other workgroup's completed counter updates.
-__device__ void finish_launch(const SearchArgs &a, int level)
+// L2): everything workgroups exchange within a launch is written and read
+// with agent-scope atomics, performed at the coherence point.  The workgroup
+// barrier waits until this workgroup's atomics have completed before thread 0
+// takes its ticket, and the ticket counter is one agent-scope atomic, so the
+// workgroup that draws the last ticket observes every other workgroup's
+// completed writes.
+__device__ bool last_workgroup(uint32_t *done)
 {
     __shared__ int s_last;
-    if (level != 0)
-        return;
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t nblocks = gridDim.x * gridDim.y;
-        s_last = atomicAdd(a.done, 1u) == nblocks - 1;
+        s_last = atomicAdd(done, 1u) == nblocks - 1;
     }
     __syncthreads();
-    if (s_last)
-        finalize(a);
+    return s_last != 0;
 }
 
-// Levels L-1 .. coarse_lo of every pair, one 1024-thread workgroup per pair.
-__global__ __launch_bounds__(1024) void k_search_coarse(SearchArgs a)
+// Exhaustive search of the coarse levels.  The i-th coarsest level (i <
+// coarse_n) is searched over every shift within radius R = 2^(i+1) - 1, which
+// holds every candidate the coarse-to-fine search can test there.  Workgroup
+// (item, pair) computes the errors of one row (cy fixed, cx = -R..R) of one
+// level's window; the last workgroup to finish walks the windows coarse to
+// fine exactly as the nine-candidate search would, recording each level's
+// nine errors and base.
+__global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
 {
-    __shared__ uint32_t red[16][9];
-    __shared__ uint32_t tot[9];
-    const int pair = blockIdx.x;
+    constexpr int kMaxR = 7;
+    __shared__ uint32_t red[4][2 * kMaxR + 1];
+    const int pair = blockIdx.y;
     const int wave = wave_id();
     const int lane = threadIdx.x & 63;
     const Geometry &g = a.g;
-    uint32_t *state = a.state + (int64_t)pair * a.state_stride;
-    int32_t *bases = (int32_t *)(state + (int64_t)g.L * kCounterWords);
-    int bx = 0, by = 0;
-    for (int l = g.L - 1; l >= a.coarse_lo; --l) {
-        const LevelGeom &lv = g.lv[l];
-        const UnitPlan p = plan_level(lv, a.rows_per_stream);
-        uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        for (int u = wave; u < p.units; u += 16)
-            search_unit(a.ref[pair], a.mov[pair], lv, bx, by, u, p.cw_log2, a.rows_per_stream, p.units_x, acc);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const uint32_t s = wave_sum(acc[i]);
-            if (lane == 0)
-                red[wave][i] = s;
-        }
-        __syncthreads();
-        if (threadIdx.x < 9) {
-            uint32_t s = 0;
-            for (int w = 0; w < 16; ++w)
-                s += red[w][threadIdx.x];
-            tot[threadIdx.x] = s;
-            state[l * kCounterWords + threadIdx.x] = s;  // copy 0 holds the total
-        }
-        __syncthreads();
-        const int best = argmin9(tot);
-        if (threadIdx.x == 0) {
-            bases[2 * l] = bx;
-            bases[2 * l + 1] = by;
-        }
-        bx = 2 * (bx + best % 3 - 1);
-        by = 2 * (by + best / 3 - 1);
-        __syncthreads();
+
+    int item = blockIdx.x, i = 0;
+    while (item >= 2 * coarse_radius(i) + 1) {
+        item -= 2 * coarse_radius(i) + 1;
+        ++i;
     }
-    finish_launch(a, a.coarse_lo);
+    const int R = coarse_radius(i);
+    const int cy = item - R;
+    const LevelGeom &lv = g.lv[g.L - 1 - i];
+    const int n32 = 2 * lv.wpr, h = lv.h;
+    const uint32_t *tr = (const uint32_t *)(a.ref[pair] + lv.tb_off);
+    const uint32_t *er = (const uint32_t *)(a.ref[pair] + lv.eb_off);
+    const uint32_t *tm = (const uint32_t *)(a.mov[pair] + lv.tb_off);
+    const uint32_t *em = (const uint32_t *)(a.mov[pair] + lv.eb_off);
+
+    // 256 lanes as CW columns x (256 / CW) row streams.
+    int cw_log2 = 0;
+    while ((1 << cw_log2) < n32 && cw_log2 < 6)
+        ++cw_log2;
+    const int cw = 1 << cw_log2;
+    const int streams = 256 >> cw_log2;
+    const int col = threadIdx.x & (cw - 1), stream = threadIdx.x >> cw_log2;
+
+    uint32_t acc[2 * kMaxR + 1];
+#pragma unroll
+    for (int c = 0; c < 2 * kMaxR + 1; ++c)
+        acc[c] = 0u;
+    constexpr int kRows = 8;  // rows per batch, all loads issued first
+    for (int k = col; k < n32; k += cw) {
+        for (int y0 = stream; y0 < h; y0 += kRows * streams) {
+            uint32_t t[kRows], e[kRows], mt[kRows][3], me[kRows][3];
+#pragma unroll
+            for (int b = 0; b < kRows; ++b) {
+                const int y = y0 + b * streams;
+                const bool ok = y < h;
+                t[b] = ok ? tr[y * n32 + k] : 0u;
+                e[b] = ok ? er[y * n32 + k] : 0u;
+                // Shift cx takes bits [32k - cx, 32k - cx + 32) of moving row y - cy:
+                // words k-1 .. k+1, as |cx| <= 7.
+                load3(tm, ok ? y - cy : -1, h, n32, k - 1, mt[b]);
+                load3(em, ok ? y - cy : -1, h, n32, k - 1, me[b]);
+            }
+#pragma unroll
+            for (int b = 0; b < kRows; ++b) {
+#pragma unroll
+                for (int c = 0; c < 2 * kMaxR + 1; ++c) {
+                    const int cx = c - kMaxR;
+                    if (cx >= -R && cx <= R) {
+                        const int o = 32 - cx;  // bit offset from the start of word k-1
+                        const uint32_t st = o < 32 ? funnel(mt[b][1], mt[b][0], o) : funnel(mt[b][2], mt[b][1], o - 32);
+                        const uint32_t se = o < 32 ? funnel(me[b][1], me[b][0], o) : funnel(me[b][2], me[b][1], o - 32);
+                        acc[c] += __builtin_popcount((t[b] ^ st) & e[b] & se);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2 * kMaxR + 1; ++c) {
+        const uint32_t s = wave_sum(acc[c]);
+        if (lane == 0)
+            red[wave][c] = s;
+    }
+    __syncthreads();
+    uint32_t *surf = pair_surface(a, pair) + coarse_surface_offset(i);
+    if ((int)threadIdx.x < 2 * R + 1) {
+        const int c = threadIdx.x + kMaxR - R;
+        store_shared(surf + (cy + R) * (2 * R + 1) + threadIdx.x,
+                     red[0][c] + red[1][c] + red[2][c] + red[3][c]);
+    }
+
+    if (!last_workgroup(a.done))
+        return;
+    // Walk the windows: the same candidates, order and tie-break as the
+    // nine-candidate search, for every pair.  All surfaces are fetched at once.
+    __shared__ uint32_t ssurf[kMaxStack * kSurfWords];
+    for (int q = threadIdx.x; q < a.npairs * kSurfWords; q += blockDim.x)
+        ssurf[q] = load_shared(pair_surface(a, q / kSurfWords) + q % kSurfWords);
+    __syncthreads();
+    if ((int)threadIdx.x < a.npairs) {
+        const int p = threadIdx.x;
+        uint32_t *state = pair_state(a, p);
+        int32_t *bases = pair_bases(a, p);
+        const uint32_t *sp = ssurf + p * kSurfWords;
+        int bx = 0, by = 0;
+        for (int ii = 0; ii < a.coarse_n; ++ii) {
+            const int l = g.L - 1 - ii, RR = coarse_radius(ii), side = 2 * RR + 1;
+            const uint32_t *w = sp + coarse_surface_offset(ii);
+            uint32_t c[9];
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx)
+                    c[(dy + 1) * 3 + dx + 1] = w[(by + dy + RR) * side + (bx + dx + RR)];
+            for (int q = 0; q < 9; ++q)
+                store_shared(state + l * kCounterWords + q, c[q]);  // copy 0 holds the total
+            store_shared((uint32_t *)bases + 2 * l, (uint32_t)bx);
+            store_shared((uint32_t *)bases + 2 * l + 1, (uint32_t)by);
+            const int best = argmin9(c);
+            bx = 2 * (bx + best % 3 - 1);
+            by = 2 * (by + best / 3 - 1);
+        }
+    }
+    if (a.coarse_n == g.L) {
+        __syncthreads();
+        finalize(a);
+    }
 }
 
-// One large level of every pair: grid (workgroups per pair, pairs).
+// One level below the coarse ones, for every pair: grid (workgroups per pair, pairs).
 __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
 {
     __shared__ uint32_t cnt[kCounterWords];
+    __shared__ int sprev[2];
     __shared__ int sbase[2];
     __shared__ uint32_t red[4][9];
     const int pair = blockIdx.y;
@@ -771,28 +919,36 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
     const int lane = threadIdx.x & 63;
     const Geometry &g = a.g;
     const int l = a.level;
-    uint32_t *state = a.state + (int64_t)pair * a.state_stride;
-    int32_t *bases = (int32_t *)(state + (int64_t)g.L * kCounterWords);
+    uint32_t *state = pair_state(a, pair);
+    int32_t *bases = pair_bases(a, pair);
 
-    // Base of this level = twice the winner of the level above.
-    if (threadIdx.x < kCounterWords)
-        cnt[threadIdx.x] = state[(l + 1) * kCounterWords + threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t c[9];
-        for (int i = 0; i < 9; ++i) {
-            uint32_t s = 0;
-            for (int k = 0; k < kCopies; ++k)
-                s += cnt[k * 9 + i];
-            c[i] = s;
+    // Base of this level = twice the winner of the level above (one round trip).
+    if (l < g.L - 1) {
+        if (threadIdx.x < kCounterWords)
+            cnt[threadIdx.x] = state[(l + 1) * kCounterWords + threadIdx.x];
+        else if (threadIdx.x < kCounterWords + 2)
+            sprev[threadIdx.x - kCounterWords] = bases[2 * (l + 1) + threadIdx.x - kCounterWords];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t c[9];
+            for (int i = 0; i < 9; ++i) {
+                uint32_t s = 0;
+                for (int k = 0; k < kCopies; ++k)
+                    s += cnt[k * 9 + i];
+                c[i] = s;
+            }
+            const int best = argmin9(c);
+            sbase[0] = 2 * (sprev[0] + best % 3 - 1);
+            sbase[1] = 2 * (sprev[1] + best / 3 - 1);
+            if (blockIdx.x == 0) {
+                bases[2 * l] = sbase[0];
+                bases[2 * l + 1] = sbase[1];
+            }
         }
-        const int best = argmin9(c);
-        sbase[0] = 2 * (bases[2 * (l + 1)] + best % 3 - 1);
-        sbase[1] = 2 * (bases[2 * (l + 1) + 1] + best / 3 - 1);
-        if (blockIdx.x == 0) {
-            bases[2 * l] = sbase[0];
-            bases[2 * l + 1] = sbase[1];
-        }
+    } else if (threadIdx.x == 0) {
+        sbase[0] = sbase[1] = 0;
+        if (blockIdx.x == 0)
+            bases[2 * l] = bases[2 * l + 1] = 0;
     }
     __syncthreads();
 
@@ -816,7 +972,8 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
         if (s)
             atomicAdd(state + l * kCounterWords + (blockIdx.x % kCopies) * 9 + threadIdx.x, s);
     }
-    finish_launch(a, l);
+    if (l == 0 && last_workgroup(a.done + 1))
+        finalize(a);
 }
 
 }  // namespace
@@ -845,7 +1002,8 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     a.tiles_x = (a.g.W + kTileW - 1) / kTileW;
     a.tiles_y = (a.g.H + kTileH - 1) / kTileH;
     const int64_t total = (int64_t)a.tiles_x * a.tiles_y * a.n;
-    const int64_t want = (int64_t)cus * 4;
+    // Three workgroups fit on a compute unit at this kernel's register count.
+    const int64_t want = (int64_t)cus * 3;
     int64_t per = (total + want - 1) / want;
     per = per < 1 ? 1 : per;
     a.tiles_per_block = (int32_t)per;
@@ -883,30 +1041,33 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
     return hipGetLastError();
 }
 
-// Level sizes (in dwords) up to this many are searched by the single-workgroup
-// coarse kernel; larger levels get a grid-wide launch each.
-constexpr int64_t kCoarseDwords = 4096;
+// The i-th coarsest level is searched exhaustively when i < kCoarseLevels and
+// its window rows stay cheap for one workgroup: at most this many dwords.
+constexpr int64_t kCoarseDwords = 8192;
 
 hipError_t launch_search(SearchArgs a, hipStream_t s)
 {
     const Geometry &g = a.g;
-    int lo = g.L;
-    while (lo > 0 && (int64_t)2 * g.lv[lo - 1].wpr * g.lv[lo - 1].h <= kCoarseDwords)
-        --lo;
-    if (lo == g.L)
-        lo = g.L - 1;  // the coarsest level always runs in the coarse kernel
-    a.coarse_lo = lo;
-    a.rows_per_stream = 4;
-    {
-        ProfScope prof_("k_search_coarse", s);
-        hipLaunchKernelGGL(k_search_coarse, dim3(a.npairs), dim3(1024), 0, s, a);
+    int cn = 0;
+    while (cn < kCoarseLevels && cn < g.L && (int64_t)2 * g.lv[g.L - 1 - cn].wpr * g.lv[g.L - 1 - cn].h <= kCoarseDwords)
+        ++cn;
+    a.coarse_n = cn;
+    hipError_t e = hipSuccess;
+    if (cn > 0) {
+        int items = 0;
+        for (int i = 0; i < cn; ++i)
+            items += 2 * coarse_radius(i) + 1;
+        {
+            ProfScope prof_("k_search_coarse", s);
+            hipLaunchKernelGGL(k_search_coarse, dim3(items, a.npairs), dim3(256), 0, s, a);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    for (int l = lo - 1; l >= 0; --l) {
-        // 8 rows per stream, fewer when that leaves too few work units to fill the chip.
-        int rows = 8;
+    for (int l = g.L - 1 - cn; l >= 0; --l) {
+        // 16 rows per stream, fewer when that leaves too few work units to fill the chip.
+        int rows = 16;
         while (rows > 4 && (int64_t)plan_level(g.lv[l], rows).units * a.npairs < 4096)
             rows >>= 1;
         a.level = l;

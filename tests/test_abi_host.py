@@ -71,8 +71,9 @@ def test_layout_is_consistent(mtb, w, h, L):
     end = 0
     for l in range(L):
         assert lay.level_width[l] == w >> l and lay.level_height[l] == h >> l
-        assert lay.words_per_row[l] == -(-(w >> l) // 64)
+        assert lay.words_per_row[l] == 2 * -(-(w >> l) // 128)
         assert lay.gray_pitch[l] == 64 * lay.words_per_row[l]
+        assert lay.gray_pitch[l] % 128 == 0
         assert lay.gray_offset[l] % 256 == 0 and lay.gray_offset[l] >= end
         end = lay.gray_offset[l] + lay.gray_pitch[l] * lay.level_height[l]
     assert lay.hist_offset >= end and lay.hist_offset % 256 == 0
@@ -92,7 +93,9 @@ def test_layout_is_consistent(mtb, w, h, L):
 def test_workspace_sizes(mtb):
     P, B = mtb.mtb_pyramid_bytes(6000, 4000, 7), mtb.mtb_bitmaps_bytes(6000, 4000, 7)
     ws = mtb.mtb_stack_workspace_bytes(7, 6000, 4000, 7)
-    assert ws >= 7 * (P + B) + 6 * mtb.mtb_pair_workspace_bytes(7)
+    # Pyramids and bitmaps of all seven images plus six pairs' search state
+    # (the pair workspace minus its 256-byte ticket block).
+    assert ws >= 7 * (P + B) + 6 * (mtb.mtb_pair_workspace_bytes(7) - 256)
     assert mtb.mtb_pair_workspace_bytes(7) >= 4 * (7 * 72 + 14)
     assert mtb.mtb_stack_workspace_bytes(0, 10, 10, 1) == 0
     assert mtb.mtb_stack_workspace_bytes(33, 10, 10, 1) == 0
