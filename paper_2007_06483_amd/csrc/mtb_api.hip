@@ -180,7 +180,7 @@ size_t mtb_pair_workspace_bytes(int32_t levels)
 {
     if (levels < 1 || levels > kMaxLevels)
         return 0;
-    return (size_t)(state_stride_words(levels) + kAlign / 4) * 4;  // state, then the done counter
+    return (size_t)(state_stride_words(levels) + align_up(kTicketWords, kAlign / 4)) * 4;  // state, tickets
 }
 
 size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t levels)
@@ -188,9 +188,9 @@ size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32
     Geometry g;
     if (n < 1 || n > kMaxStack || !make_geometry(width, height, levels, &g))
         return 0;
-    // pyramids, bitmaps, search state, done counter, plus slack to align the start
+    // pyramids, bitmaps, search state, ticket counters, plus slack to align the start
     return (size_t)(n * (g.pyramid_bytes + g.bitmaps_bytes) + (n - 1) * state_stride_words(levels) * 4 +
-                    2 * kAlign);
+                    align_up(4 * kTicketWords, kAlign) + kAlign);
 }
 
 mtb_status mtb_build_pyramid(const uint8_t *d_rgb, int32_t width, int32_t height,
@@ -274,7 +274,7 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
     ZeroArgs z;
     memset(&z, 0, sizeof(z));
     z.ptr[0] = state;
-    z.words[0] = state_stride_words(levels) + 2;  // counters, bases, surfaces, ticket counters
+    z.words[0] = state_stride_words(levels) + kTicketWords;  // counters, bases, surfaces, tickets
     z.count = 1;
     if (launch_zero(z, s) != hipSuccess)
         return MTB_ERR_DEVICE;
@@ -294,7 +294,7 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
     a.out.trace = d_trace;
     a.out.level_shifts = d_level_shifts;
     a.g = g;
-    return device_status(launch_search(a, s));
+    return device_status(launch_search(a, cus, s));
 }
 
 mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
@@ -342,7 +342,7 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
         z.words[i] = (int64_t)levels * 256;
     }
     z.ptr[n] = state;
-    z.words[n] = sstride * npairs + 2;  // every pair's search state, then the ticket counters
+    z.words[n] = sstride * npairs + kTicketWords;  // every pair's search state, then the tickets
     z.count = n + 1;
     if (npairs == 0) {
         // A lone image is its own reference: its outputs are zero and there is nothing to search.
@@ -407,7 +407,7 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
     sa.out.trace = d_trace;
     sa.out.level_shifts = nullptr;
     sa.g = g;
-    return device_status(launch_search(sa, s));
+    return device_status(launch_search(sa, cus, s));
 }
 
 }  // extern "C"

@@ -21,7 +21,7 @@ constexpr int kTileW = 256;
 
 // Search counters are spread over this many copies per (pair, level) so that
 // concurrent workgroups do not all add into the same nine words.
-constexpr int kCopies = 8;
+constexpr int kCopies = 16;
 // Per pair and level: kCopies x 9 uint32 counters.
 constexpr int kCounterWords = kCopies * 9;
 
@@ -97,10 +97,12 @@ constexpr int kSurfWords = 3 * 3 + 7 * 7 + 15 * 15;
 
 // Per pair the search state is: counters uint32[L][kCounterWords], then
 // base int32[L][2] (the centre of each level's nine candidates), then the
-// coarse error surfaces uint32[kSurfWords].  After every pair's state come two
-// ticket counters: workgroups finished in the coarse launch and in the
-// level-0 launch.
+// coarse error surfaces uint32[kSurfWords].  After every pair's state come the
+// ticket counters of the coarse launch and of the level-0 launch: each
+// kTicketGroups group counters and one counter of completed groups.
 inline int64_t pair_state_words(int32_t L) { return (int64_t)L * kCounterWords + 2 * L + kSurfWords; }
+constexpr int kTicketGroups = 32;
+constexpr int kTicketWords = 2 * (kTicketGroups + 1);
 
 // Where the search writes its results; the last workgroup of the launch
 // that searches level 0 fills them in.
@@ -118,7 +120,7 @@ struct SearchArgs {
     const uint8_t *ref[kMaxStack];   // bitmaps buffer of each pair's reference
     const uint8_t *mov[kMaxStack];   // bitmaps buffer of each pair's moving image
     uint32_t *state;                 // pair p's state at state + p * state_stride
-    uint32_t *done;                  // [0] coarse-launch tickets, [1] level-0 launch tickets
+    uint32_t *done;                  // ticket counters: coarse launch, then level-0 launch
     int64_t state_stride;            // uint32 words
     int32_t npairs;
     int32_t level;                   // fine kernel: the level searched
@@ -155,6 +157,6 @@ hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s);
 hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s);
 // Searches every level of every pair and writes a.out; a.state and *a.done
 // must be zero.
-hipError_t launch_search(SearchArgs a, hipStream_t s);
+hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s);
 
 }  // namespace mtb

@@ -567,9 +567,15 @@ __device__ __forceinline__ void load3(const uint32_t *plane, int j, int h, int n
     }
 }
 
+// Loads and scoring of one batch of four reference rows (and the moving rows
+// one below each, ddy = -1) of a work unit.
+struct RowBatch {
+    uint32_t rt[4], re[4], mt[4][3], me[4][3];
+};
+
 // Nine candidate errors of one work unit.  A wavefront covers CW = 2^cw_log2
-// dword columns and 64 / CW row streams; each stream walks `rows` rows.  Rows
-// are processed four at a time with all of their loads issued first.
+// dword columns and 64 / CW row streams; each stream walks `rows` rows, four
+// at a time, with the next batch's loads in flight while one batch is scored.
 __device__ void search_unit(const uint8_t *ref, const uint8_t *mov, const LevelGeom &lv, int bx,
                             int by, int unit, int cw_log2, int rows, int units_x, uint32_t acc[9])
 {
@@ -592,39 +598,30 @@ __device__ void search_unit(const uint8_t *ref, const uint8_t *mov, const LevelG
     const uint32_t r = (uint32_t)u & 31u;
     const bool col_ok = k < n32;
 
-    // Moving rows seen by reference row y: y - by - ddy for ddy = +1, 0, -1.
-    uint32_t at[3], ae[3], bt[3], be[3];
-    {
-        uint32_t w[3];
-        load3(tm, y_begin - by - 1, h, n32, q, w);
-        shift3(w[0], w[1], w[2], r, at);
-        load3(em, y_begin - by - 1, h, n32, q, w);
-        shift3(w[0], w[1], w[2], r, ae);
-        load3(tm, y_begin - by, h, n32, q, w);
-        shift3(w[0], w[1], w[2], r, bt);
-        load3(em, y_begin - by, h, n32, q, w);
-        shift3(w[0], w[1], w[2], r, be);
-    }
-    for (int y = y_begin; y < y_end; y += 4) {
-        uint32_t rt[4], re[4], mt[4][3], me[4][3];
+    auto load = [&](int y, RowBatch &b) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const bool ok = y + i < y_end;
-            rt[i] = (ok && col_ok) ? tr[(y + i) * n32 + k] : 0u;
-            re[i] = (ok && col_ok) ? er[(y + i) * n32 + k] : 0u;
-            load3(tm, ok ? y + i - by + 1 : -1, h, n32, q, mt[i]);
-            load3(em, ok ? y + i - by + 1 : -1, h, n32, q, me[i]);
+            b.rt[i] = (ok && col_ok) ? tr[(y + i) * n32 + k] : 0u;
+            b.re[i] = (ok && col_ok) ? er[(y + i) * n32 + k] : 0u;
+            load3(tm, ok ? y + i - by + 1 : -1, h, n32, q, b.mt[i]);
+            load3(em, ok ? y + i - by + 1 : -1, h, n32, q, b.me[i]);
         }
+    };
+
+    // Moving rows seen by reference row y: y - by - ddy for ddy = +1, 0, -1.
+    uint32_t at[3], ae[3], bt[3], be[3];
+    auto score = [&](const RowBatch &b) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             uint32_t ct[3], ce[3];
-            shift3(mt[i][0], mt[i][1], mt[i][2], r, ct);
-            shift3(me[i][0], me[i][1], me[i][2], r, ce);
+            shift3(b.mt[i][0], b.mt[i][1], b.mt[i][2], r, ct);
+            shift3(b.me[i][0], b.me[i][1], b.me[i][2], r, ce);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                acc[d] += __builtin_popcount((rt[i] ^ ct[d]) & re[i] & ce[d]);      // ddy = -1
-                acc[3 + d] += __builtin_popcount((rt[i] ^ bt[d]) & re[i] & be[d]);  // ddy = 0
-                acc[6 + d] += __builtin_popcount((rt[i] ^ at[d]) & re[i] & ae[d]);  // ddy = +1
+                acc[d] += __builtin_popcount((b.rt[i] ^ ct[d]) & b.re[i] & ce[d]);      // ddy = -1
+                acc[3 + d] += __builtin_popcount((b.rt[i] ^ bt[d]) & b.re[i] & be[d]);  // ddy = 0
+                acc[6 + d] += __builtin_popcount((b.rt[i] ^ at[d]) & b.re[i] & ae[d]);  // ddy = +1
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -634,6 +631,30 @@ __device__ void search_unit(const uint8_t *ref, const uint8_t *mov, const LevelG
                 be[d] = ce[d];
             }
         }
+    };
+
+    RowBatch b0, b1;
+    {
+        uint32_t w[4][3];
+        load3(tm, y_begin - by - 1, h, n32, q, w[0]);
+        load3(em, y_begin - by - 1, h, n32, q, w[1]);
+        load3(tm, y_begin - by, h, n32, q, w[2]);
+        load3(em, y_begin - by, h, n32, q, w[3]);
+        load(y_begin, b0);
+        shift3(w[0][0], w[0][1], w[0][2], r, at);
+        shift3(w[1][0], w[1][1], w[1][2], r, ae);
+        shift3(w[2][0], w[2][1], w[2][2], r, bt);
+        shift3(w[3][0], w[3][1], w[3][2], r, be);
+    }
+    for (int y = y_begin; y < y_end; y += 8) {
+        if (y + 4 < y_end)
+            load(y + 4, b1);
+        score(b0);
+        if (y + 4 >= y_end)
+            break;
+        if (y + 8 < y_end)
+            load(y + 8, b0);
+        score(b1);
     }
 }
 
@@ -763,38 +784,66 @@ __device__ void finalize(const SearchArgs &a)
     }
 }
 
-// Takes a ticket from *done once this workgroup's shared writes have
-// completed; true in the workgroup that takes the last ticket of the launch.
+// True in the workgroup that finishes last in the launch.  Tickets are taken
+// in two stages so that no single counter receives more than about
+// gridsize / kTicketGroups atomics: workgroup b counts into group b %
+// kTicketGroups, and the last arrival of each group counts into t[G].
 //
 // Ordering without device-wide fences (which on gfx950 write back the whole
 // L2): everything workgroups exchange within a launch is written and read
 // with agent-scope atomics, performed at the coherence point.  The workgroup
 // barrier waits until this workgroup's atomics have completed before thread 0
-// takes its ticket, and the ticket counter is one agent-scope atomic, so the
-// workgroup that draws the last ticket observes every other workgroup's
-// completed writes.
-__device__ bool last_workgroup(uint32_t *done)
+// takes its ticket, and each ticket counter is a single agent-scope atomic,
+// so the workgroup that draws the last ticket observes every other
+// workgroup's completed writes.
+__device__ bool last_workgroup(uint32_t *t)
 {
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t nblocks = gridDim.x * gridDim.y;
-        s_last = atomicAdd(done, 1u) == nblocks - 1;
+        const uint32_t n = gridDim.x * gridDim.y;
+        const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
+        const uint32_t grp = b % kTicketGroups;
+        const uint32_t members = (n - grp + kTicketGroups - 1) / kTicketGroups;
+        const uint32_t groups = n < (uint32_t)kTicketGroups ? n : (uint32_t)kTicketGroups;
+        s_last = 0;
+        if (atomicAdd(t + grp, 1u) == members - 1)
+            s_last = atomicAdd(t + kTicketGroups, 1u) == groups - 1;
     }
     __syncthreads();
     return s_last != 0;
 }
 
+// Column width (log2, in dwords) and row slabs of a coarse level handled by
+// 256-lane workgroups: CW = 2^cw_log2 columns x 256 / CW row streams, each
+// stream scoring 8 rows of a slab.
+__host__ __device__ __forceinline__ int coarse_cw_log2(const LevelGeom &lv)
+{
+    int c = 0;
+    while ((1 << c) < 2 * lv.wpr && c < 6)
+        ++c;
+    return c;
+}
+
+__host__ __device__ __forceinline__ int coarse_slab_rows(const LevelGeom &lv) { return 8 * (256 >> coarse_cw_log2(lv)); }
+
+__host__ __device__ __forceinline__ int coarse_slabs(const LevelGeom &lv)
+{
+    const int rows = coarse_slab_rows(lv);
+    return (lv.h + rows - 1) / rows;
+}
+
 // Exhaustive search of the coarse levels.  The i-th coarsest level (i <
 // coarse_n) is searched over every shift within radius R = 2^(i+1) - 1, which
 // holds every candidate the coarse-to-fine search can test there.  Workgroup
-// (item, pair) computes the errors of one row (cy fixed, cx = -R..R) of one
-// level's window; the last workgroup to finish walks the windows coarse to
-// fine exactly as the nine-candidate search would, recording each level's
-// nine errors and base.
+// (item, pair) adds the errors of one row of a level's window (cy fixed,
+// cx = -R..R) over one slab of rows into the pair's error surface; the last
+// workgroup to finish walks the windows coarse to fine exactly as the
+// nine-candidate search would, recording each level's nine errors and base.
 __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
 {
     constexpr int kMaxR = 7;
+    constexpr int kRows = 8;  // rows per stream and slab, all loads issued first
     __shared__ uint32_t red[4][2 * kMaxR + 1];
     const int pair = blockIdx.y;
     const int wave = wave_id();
@@ -802,23 +851,25 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
     const Geometry &g = a.g;
 
     int item = blockIdx.x, i = 0;
-    while (item >= 2 * coarse_radius(i) + 1) {
-        item -= 2 * coarse_radius(i) + 1;
+    for (;;) {
+        const int cnt = (2 * coarse_radius(i) + 1) * coarse_slabs(g.lv[g.L - 1 - i]);
+        if (item < cnt)
+            break;
+        item -= cnt;
         ++i;
     }
-    const int R = coarse_radius(i);
-    const int cy = item - R;
     const LevelGeom &lv = g.lv[g.L - 1 - i];
+    const int R = coarse_radius(i);
+    const int slabs = coarse_slabs(lv);
+    const int cy = item / slabs - R;
+    const int y_lo = (item % slabs) * coarse_slab_rows(lv);
     const int n32 = 2 * lv.wpr, h = lv.h;
     const uint32_t *tr = (const uint32_t *)(a.ref[pair] + lv.tb_off);
     const uint32_t *er = (const uint32_t *)(a.ref[pair] + lv.eb_off);
     const uint32_t *tm = (const uint32_t *)(a.mov[pair] + lv.tb_off);
     const uint32_t *em = (const uint32_t *)(a.mov[pair] + lv.eb_off);
 
-    // 256 lanes as CW columns x (256 / CW) row streams.
-    int cw_log2 = 0;
-    while ((1 << cw_log2) < n32 && cw_log2 < 6)
-        ++cw_log2;
+    const int cw_log2 = coarse_cw_log2(lv);
     const int cw = 1 << cw_log2;
     const int streams = 256 >> cw_log2;
     const int col = threadIdx.x & (cw - 1), stream = threadIdx.x >> cw_log2;
@@ -827,32 +878,29 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
 #pragma unroll
     for (int c = 0; c < 2 * kMaxR + 1; ++c)
         acc[c] = 0u;
-    constexpr int kRows = 8;  // rows per batch, all loads issued first
     for (int k = col; k < n32; k += cw) {
-        for (int y0 = stream; y0 < h; y0 += kRows * streams) {
-            uint32_t t[kRows], e[kRows], mt[kRows][3], me[kRows][3];
+        uint32_t t[kRows], e[kRows], mt[kRows][3], me[kRows][3];
 #pragma unroll
-            for (int b = 0; b < kRows; ++b) {
-                const int y = y0 + b * streams;
-                const bool ok = y < h;
-                t[b] = ok ? tr[y * n32 + k] : 0u;
-                e[b] = ok ? er[y * n32 + k] : 0u;
-                // Shift cx takes bits [32k - cx, 32k - cx + 32) of moving row y - cy:
-                // words k-1 .. k+1, as |cx| <= 7.
-                load3(tm, ok ? y - cy : -1, h, n32, k - 1, mt[b]);
-                load3(em, ok ? y - cy : -1, h, n32, k - 1, me[b]);
-            }
+        for (int b = 0; b < kRows; ++b) {
+            const int y = y_lo + stream + b * streams;
+            const bool ok = y < h;
+            t[b] = ok ? tr[y * n32 + k] : 0u;
+            e[b] = ok ? er[y * n32 + k] : 0u;
+            // Shift cx takes bits [32k - cx, 32k - cx + 32) of moving row y - cy:
+            // words k-1 .. k+1, as |cx| <= 7.
+            load3(tm, ok ? y - cy : -1, h, n32, k - 1, mt[b]);
+            load3(em, ok ? y - cy : -1, h, n32, k - 1, me[b]);
+        }
 #pragma unroll
-            for (int b = 0; b < kRows; ++b) {
+        for (int b = 0; b < kRows; ++b) {
 #pragma unroll
-                for (int c = 0; c < 2 * kMaxR + 1; ++c) {
-                    const int cx = c - kMaxR;
-                    if (cx >= -R && cx <= R) {
-                        const int o = 32 - cx;  // bit offset from the start of word k-1
-                        const uint32_t st = o < 32 ? funnel(mt[b][1], mt[b][0], o) : funnel(mt[b][2], mt[b][1], o - 32);
-                        const uint32_t se = o < 32 ? funnel(me[b][1], me[b][0], o) : funnel(me[b][2], me[b][1], o - 32);
-                        acc[c] += __builtin_popcount((t[b] ^ st) & e[b] & se);
-                    }
+            for (int c = 0; c < 2 * kMaxR + 1; ++c) {
+                const int cx = c - kMaxR;
+                if (cx >= -R && cx <= R) {
+                    const int o = 32 - cx;  // bit offset from the start of word k-1
+                    const uint32_t st = o < 32 ? funnel(mt[b][1], mt[b][0], o) : funnel(mt[b][2], mt[b][1], o - 32);
+                    const uint32_t se = o < 32 ? funnel(me[b][1], me[b][0], o) : funnel(me[b][2], me[b][1], o - 32);
+                    acc[c] += __builtin_popcount((t[b] ^ st) & e[b] & se);
                 }
             }
         }
@@ -867,8 +915,9 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
     uint32_t *surf = pair_surface(a, pair) + coarse_surface_offset(i);
     if ((int)threadIdx.x < 2 * R + 1) {
         const int c = threadIdx.x + kMaxR - R;
-        store_shared(surf + (cy + R) * (2 * R + 1) + threadIdx.x,
-                     red[0][c] + red[1][c] + red[2][c] + red[3][c]);
+        const uint32_t v = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+        if (v)
+            atomicAdd(surf + (cy + R) * (2 * R + 1) + threadIdx.x, v);
     }
 
     if (!last_workgroup(a.done))
@@ -972,7 +1021,7 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
         if (s)
             atomicAdd(state + l * kCounterWords + (blockIdx.x % kCopies) * 9 + threadIdx.x, s);
     }
-    if (l == 0 && last_workgroup(a.done + 1))
+    if (l == 0 && last_workgroup(a.done + kTicketGroups + 1))
         finalize(a);
 }
 
@@ -1045,7 +1094,7 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
 // its window rows stay cheap for one workgroup: at most this many dwords.
 constexpr int64_t kCoarseDwords = 8192;
 
-hipError_t launch_search(SearchArgs a, hipStream_t s)
+hipError_t launch_search(SearchArgs a, int cus, hipStream_t s)
 {
     const Geometry &g = a.g;
     int cn = 0;
@@ -1056,7 +1105,7 @@ hipError_t launch_search(SearchArgs a, hipStream_t s)
     if (cn > 0) {
         int items = 0;
         for (int i = 0; i < cn; ++i)
-            items += 2 * coarse_radius(i) + 1;
+            items += (2 * coarse_radius(i) + 1) * coarse_slabs(g.lv[g.L - 1 - i]);
         {
             ProfScope prof_("k_search_coarse", s);
             hipLaunchKernelGGL(k_search_coarse, dim3(items, a.npairs), dim3(256), 0, s, a);
@@ -1066,10 +1115,12 @@ hipError_t launch_search(SearchArgs a, hipStream_t s)
             return e;
     }
     for (int l = g.L - 1 - cn; l >= 0; --l) {
-        // 16 rows per stream, fewer when that leaves too few work units to fill the chip.
-        int rows = 16;
-        while (rows > 4 && (int64_t)plan_level(g.lv[l], rows).units * a.npairs < 4096)
-            rows >>= 1;
+        // Rows per stream: the fewest (at least 4) that keep the grid within one
+        // round of resident workgroups (three per compute unit at this kernel's
+        // register count), so no workgroup waits for another to finish.
+        int rows = 4;
+        while (rows < 64 && (int64_t)(plan_level(g.lv[l], rows).units + 3) / 4 * a.npairs > (int64_t)cus * 3)
+            rows <<= 1;
         a.level = l;
         a.rows_per_stream = rows;
         const int blocks = (plan_level(g.lv[l], rows).units + 3) / 4;
