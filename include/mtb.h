@@ -63,6 +63,7 @@ typedef enum mtb_status {
  *     (the bytes past level_width[l] are padding with no defined value);
  *   histogram: uint32 hist[levels][256] at hist_offset (Section III-B).
  * Bitmaps buffer (written by mtb_bitmaps):
+ *   the first 256 bytes are a guard with no defined value;
  *   level l threshold bitmap T and exclusion bitmap E: each level_height[l]
  *     rows of words_per_row[l] uint64 words at tb_offset[l] / eb_offset[l];
  *     pixel x of row y is bit (x % 64) of word (x / 64) of the row (least

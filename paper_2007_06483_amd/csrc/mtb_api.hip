@@ -43,7 +43,10 @@ bool make_geometry(int32_t W, int32_t H, int32_t L, Geometry *g)
     g->hist_off = off;
     off = align_up(off + (int64_t)L * 256 * 4, kAlign);
     g->pyramid_bytes = off;
-    off = 0;
+    // The search reads up to two words either side of a bitmap row (and masks
+    // them out): a leading guard keeps those reads inside the buffer before
+    // the first plane; the medians follow the last plane.
+    off = kAlign;
     for (int l = 0; l < L; ++l) {
         LevelGeom &lv = g->lv[l];
         const int64_t plane = 8 * (int64_t)lv.wpr * lv.h;
@@ -344,16 +347,14 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
     z.ptr[n] = state;
     z.words[n] = sstride * npairs + kTicketWords;  // every pair's search state, then the tickets
     z.count = n + 1;
-    if (npairs == 0) {
-        // A lone image is its own reference: its outputs are zero and there is nothing to search.
-        z.ptr[z.count] = (uint32_t *)d_shifts;
-        z.words[z.count++] = 2;
-        z.ptr[z.count] = d_errs;
-        z.words[z.count++] = 1;
-        if (d_trace) {
-            z.ptr[z.count] = d_trace;
-            z.words[z.count++] = 9 * (int64_t)levels;
-        }
+    // The reference's output rows stay zero; the search writes every other row.
+    z.ptr[z.count] = (uint32_t *)d_shifts;
+    z.words[z.count++] = 2 * (int64_t)n;
+    z.ptr[z.count] = d_errs;
+    z.words[z.count++] = n;
+    if (d_trace) {
+        z.ptr[z.count] = d_trace;
+        z.words[z.count++] = 9 * (int64_t)levels * n;
     }
     if (launch_zero(z, s) != hipSuccess)
         return MTB_ERR_DEVICE;

@@ -543,18 +543,7 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh
     return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
-// The three horizontally shifted copies (ddx = -1, 0, +1 -> index 0, 1, 2) of
-// one 32-pixel word of a moving bitmap row: bits [t, t+32) of the row with
-// t = 32k - (bx + ddx), from the three row words m0, m1, m2 starting at word
-// floor((32k - bx - 1) / 32); r = (32k - bx - 1) mod 32.
-__device__ __forceinline__ void shift3(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t r, uint32_t *s)
-{
-    s[2] = funnel(m1, m0, r);
-    s[1] = r + 1 < 32 ? funnel(m1, m0, r + 1) : m1;
-    s[0] = r + 2 < 32 ? funnel(m1, m0, r + 2) : funnel(m2, m1, r + 2 - 32);
-}
-
-// Loads the three row words for shift3 (zero outside the row and outside the level).
+// Loads row words q .. q+2 of row j of a plane (zero outside the row and outside the level).
 __device__ __forceinline__ void load3(const uint32_t *plane, int j, int h, int n32, int q, uint32_t *w)
 {
     w[0] = w[1] = w[2] = 0u;
@@ -567,18 +556,46 @@ __device__ __forceinline__ void load3(const uint32_t *plane, int j, int h, int n
     }
 }
 
-// Loads and scoring of one batch of four reference rows (and the moving rows
-// one below each, ddy = -1) of a work unit.
+// One batch of four reference rows of a work unit and, for each, the moving
+// row one below it (ddy = -1): kW words of each moving row around the lane's
+// column (see search_unit_t).
+template <int kW>
 struct RowBatch {
-    uint32_t rt[4], re[4], mt[4][3], me[4][3];
+    uint32_t rt[4], re[4], mt[4][kW], me[4][kW];
 };
+
+// The three horizontally shifted copies (ddx = -1, 0, +1 -> index 0, 1, 2) of
+// one 32-pixel word k of a moving bitmap row: bits [t, t+32) of the row with
+// t = 32k - (bx + ddx), from the row words m[0], m[1] (and m[2]) starting at
+// word floor((32k - bx - 1) / 32); r = (32k - bx - 1) mod 32 (wave-uniform).
+// kCase 0: r <= 29; kCase 1: r == 30; kCase 2: r == 31 (only this one needs m2).
+template <int kCase>
+__device__ __forceinline__ void shift3c(const uint32_t *m, uint32_t r, uint32_t *s)
+{
+    s[2] = funnel(m[1], m[0], r);
+    if (kCase == 0) {
+        s[1] = funnel(m[1], m[0], r + 1);
+        s[0] = funnel(m[1], m[0], r + 2);
+    } else if (kCase == 1) {
+        s[1] = funnel(m[1], m[0], 31);
+        s[0] = m[1];
+    } else {
+        s[1] = m[1];
+        s[0] = funnel(m[2], m[1], 1);
+    }
+}
 
 // Nine candidate errors of one work unit.  A wavefront covers CW = 2^cw_log2
 // dword columns and 64 / CW row streams; each stream walks `rows` rows, four
 // at a time, with the next batch's loads in flight while one batch is scored.
-__device__ void search_unit(const uint8_t *ref, const uint8_t *mov, const LevelGeom &lv, int bx,
-                            int by, int unit, int cw_log2, int rows, int units_x, uint32_t acc[9])
+// Loads never branch: row and column indices are clamped into the level and
+// the exclusion words of anything outside it are masked to zero, which zeroes
+// those pixels' contribution whatever their threshold bits hold.
+template <int kCase>
+__device__ void search_unit_t(const uint8_t *ref, const uint8_t *mov, const LevelGeom &lv, int bx, int by,
+                              int unit, int cw_log2, int rows, int units_x, uint32_t acc[9])
 {
+    constexpr int kW = kCase == 2 ? 3 : 2;  // moving words needed per row
     const int lane = threadIdx.x & 63;
     const int n32 = 2 * lv.wpr;
     const int h = lv.h;
@@ -589,34 +606,58 @@ __device__ void search_unit(const uint8_t *ref, const uint8_t *mov, const LevelG
     const int y_end = y_begin + rows < h ? y_begin + rows : h;
     if (y_begin >= h)
         return;
-    const uint32_t *tr = (const uint32_t *)(ref + lv.tb_off);
-    const uint32_t *er = (const uint32_t *)(ref + lv.eb_off);
-    const uint32_t *tm = (const uint32_t *)(mov + lv.tb_off);
-    const uint32_t *em = (const uint32_t *)(mov + lv.eb_off);
+    const uint8_t *tr = ref + lv.tb_off, *er = ref + lv.eb_off;
+    const uint8_t *tm = mov + lv.tb_off, *em = mov + lv.eb_off;
     const int u = -bx - 1;
-    const int q = k + (u >> 5);           // arithmetic shift: floor((-bx - 1) / 32)
+    const int q = k + (u >> 5);  // arithmetic shift: floor((-bx - 1) / 32)
     const uint32_t r = (uint32_t)u & 31u;
-    const bool col_ok = k < n32;
+    const int row_bytes = 4 * n32;
 
-    auto load = [&](int y, RowBatch &b) {
+    // Per-lane column window and validity masks, fixed for the unit.  The
+    // window's first word qc is q clamped to [-2, n32 - 1]; where that moves
+    // it, every word of the window is outside the row and masked.  Its words
+    // then lie within two words of the row, which the layout keeps inside the
+    // buffer (a 256-byte guard precedes the first plane, the medians follow
+    // the last): tm8/em8 point 8 bytes before the planes so offsets stay >= 0.
+    const uint32_t kref = 4u * (uint32_t)(k < n32 ? k : n32 - 1);
+    const uint32_t ref_ok = k < n32 ? ~0u : 0u;
+    const int qc = q < -2 ? -2 : (q > n32 - 1 ? n32 - 1 : q);
+    const uint32_t coff = 4u * (uint32_t)(qc + 2);
+    uint32_t cmask[kW];
+#pragma unroll
+    for (int i = 0; i < kW; ++i)
+        cmask[i] = (q + i >= 0 && q + i < n32) ? ~0u : 0u;
+    const uint8_t *tm8 = tm - 8, *em8 = em - 8;
+    auto load_moving = [&](int j, uint32_t *wt, uint32_t *we) {
+        const int jc = j < 0 ? 0 : (j >= h ? h - 1 : j);
+        const uint32_t rmask = j == jc ? ~0u : 0u;
+        const uint32_t off = (uint32_t)jc * (uint32_t)row_bytes + coff;
+#pragma unroll
+        for (int i = 0; i < kW; ++i) {
+            wt[i] = *(const uint32_t *)(tm8 + off + 4 * i);
+            we[i] = *(const uint32_t *)(em8 + off + 4 * i) & cmask[i] & rmask;
+        }
+    };
+    auto load = [&](int y, RowBatch<kW> &b) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const bool ok = y + i < y_end;
-            b.rt[i] = (ok && col_ok) ? tr[(y + i) * n32 + k] : 0u;
-            b.re[i] = (ok && col_ok) ? er[(y + i) * n32 + k] : 0u;
-            load3(tm, ok ? y + i - by + 1 : -1, h, n32, q, b.mt[i]);
-            load3(em, ok ? y + i - by + 1 : -1, h, n32, q, b.me[i]);
+            const int yy = y + i < y_end ? y + i : y_end - 1;
+            const uint32_t ok = y + i < y_end ? ref_ok : 0u;
+            const uint32_t base = (uint32_t)yy * (uint32_t)row_bytes + kref;
+            b.rt[i] = *(const uint32_t *)(tr + base);
+            b.re[i] = *(const uint32_t *)(er + base) & ok;
+            load_moving(yy - by + 1, b.mt[i], b.me[i]);
         }
     };
 
     // Moving rows seen by reference row y: y - by - ddy for ddy = +1, 0, -1.
     uint32_t at[3], ae[3], bt[3], be[3];
-    auto score = [&](const RowBatch &b) {
+    auto score = [&](const RowBatch<kW> &b) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             uint32_t ct[3], ce[3];
-            shift3(b.mt[i][0], b.mt[i][1], b.mt[i][2], r, ct);
-            shift3(b.me[i][0], b.me[i][1], b.me[i][2], r, ce);
+            shift3c<kCase>(b.mt[i], r, ct);
+            shift3c<kCase>(b.me[i], r, ce);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 acc[d] += __builtin_popcount((b.rt[i] ^ ct[d]) & b.re[i] & ce[d]);      // ddy = -1
@@ -633,18 +674,16 @@ __device__ void search_unit(const uint8_t *ref, const uint8_t *mov, const LevelG
         }
     };
 
-    RowBatch b0, b1;
+    RowBatch<kW> b0, b1;
     {
-        uint32_t w[4][3];
-        load3(tm, y_begin - by - 1, h, n32, q, w[0]);
-        load3(em, y_begin - by - 1, h, n32, q, w[1]);
-        load3(tm, y_begin - by, h, n32, q, w[2]);
-        load3(em, y_begin - by, h, n32, q, w[3]);
+        uint32_t w[4][kW];
+        load_moving(y_begin - by - 1, w[0], w[1]);
+        load_moving(y_begin - by, w[2], w[3]);
         load(y_begin, b0);
-        shift3(w[0][0], w[0][1], w[0][2], r, at);
-        shift3(w[1][0], w[1][1], w[1][2], r, ae);
-        shift3(w[2][0], w[2][1], w[2][2], r, bt);
-        shift3(w[3][0], w[3][1], w[3][2], r, be);
+        shift3c<kCase>(w[0], r, at);
+        shift3c<kCase>(w[1], r, ae);
+        shift3c<kCase>(w[2], r, bt);
+        shift3c<kCase>(w[3], r, be);
     }
     for (int y = y_begin; y < y_end; y += 8) {
         if (y + 4 < y_end)
@@ -656,6 +695,18 @@ __device__ void search_unit(const uint8_t *ref, const uint8_t *mov, const LevelG
             load(y + 8, b0);
         score(b1);
     }
+}
+
+__device__ __forceinline__ void search_unit(const uint8_t *ref, const uint8_t *mov, const LevelGeom &lv, int bx,
+                                            int by, int unit, int cw_log2, int rows, int units_x, uint32_t acc[9])
+{
+    const uint32_t r = (uint32_t)(-bx - 1) & 31u;
+    if (r <= 29)
+        search_unit_t<0>(ref, mov, lv, bx, by, unit, cw_log2, rows, units_x, acc);
+    else if (r == 30)
+        search_unit_t<1>(ref, mov, lv, bx, by, unit, cw_log2, rows, units_x, acc);
+    else
+        search_unit_t<2>(ref, mov, lv, bx, by, unit, cw_log2, rows, units_x, acc);
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
@@ -727,30 +778,33 @@ __device__ __forceinline__ uint32_t *pair_surface(const SearchArgs &a, int p)
 __host__ __device__ __forceinline__ int coarse_radius(int i) { return (2 << i) - 1; }
 __device__ __forceinline__ int coarse_surface_offset(int i) { return i == 0 ? 0 : (i == 1 ? 9 : 58); }
 
-// Writes the outputs from every pair's per-level counters (the sum of their
-// kCopies copies), walking from the coarsest level down.  Rows of images that
-// are not the moving image of a pair (the reference) are zero.  Run by one
-// workgroup once every counter is final.
-__device__ void finalize(const SearchArgs &a)
+// Records level l's nine errors and chosen shift in pair p's output row.
+__device__ __forceinline__ void write_level(const SearchArgs &a, int p, int l, const uint32_t *c, int sx, int sy)
 {
-    __shared__ uint32_t tot[kMaxStack * kMaxLevels * 9];
-    const int L = a.g.L;
     const SearchOutputs &o = a.out;
-    for (int r = threadIdx.x; r < o.n_out; r += blockDim.x) {
-        o.shifts[2 * r] = 0;
-        o.shifts[2 * r + 1] = 0;
-        o.errs[r] = 0u;
-        if (o.trace)
-            for (int i = 0; i < 9 * L; ++i)
-                o.trace[(int64_t)r * 9 * L + i] = 0u;
-        if (o.level_shifts)
-            for (int i = 0; i < 2 * L; ++i)
-                o.level_shifts[(int64_t)r * 2 * L + i] = 0;
+    const int64_t r = o.pair_image[p];
+    const int L = a.g.L;
+    if (o.trace)
+        for (int i = 0; i < 9; ++i)
+            o.trace[(r * L + l) * 9 + i] = c[i];
+    if (o.level_shifts) {
+        o.level_shifts[(r * L + l) * 2] = sx;
+        o.level_shifts[(r * L + l) * 2 + 1] = sy;
     }
-    // All counters of all pairs and levels at once: item (p, l, c).
-    for (int i = threadIdx.x; i < a.npairs * L * 9; i += blockDim.x) {
-        const int p = i / (L * 9), l = (i / 9) % L, c = i % 9;
-        const uint32_t *cnt = pair_state(a, p) + l * kCounterWords + c;
+    if (l == 0) {
+        o.shifts[2 * r] = sx;
+        o.shifts[2 * r + 1] = sy;
+        o.errs[r] = c[argmin9(c)];
+    }
+}
+
+// Level 0's outputs for every pair, from its counters (the sum of their
+// kCopies copies) and base.  Run by the last workgroup of the level-0 launch.
+__device__ void finalize_level0(const SearchArgs &a)
+{
+    __shared__ uint32_t tot[kMaxStack * 9];
+    for (int i = threadIdx.x; i < a.npairs * 9; i += blockDim.x) {
+        const uint32_t *cnt = pair_state(a, i / 9) + i % 9;
         uint32_t s = 0;
 #pragma unroll
         for (int k = 0; k < kCopies; ++k)
@@ -759,28 +813,13 @@ __device__ void finalize(const SearchArgs &a)
     }
     __syncthreads();
     if ((int)threadIdx.x < a.npairs) {
-        const int p = threadIdx.x, r = o.pair_image[p];
-        int bx = 0, by = 0, sx = 0, sy = 0;
-        uint32_t err = 0;
-        for (int l = L - 1; l >= 0; --l) {
-            const uint32_t *c = tot + (p * L + l) * 9;
-            const int best = argmin9(c);
-            sx = bx + best % 3 - 1;
-            sy = by + best / 3 - 1;
-            err = c[best];
-            if (o.trace)
-                for (int i = 0; i < 9; ++i)
-                    o.trace[((int64_t)r * L + l) * 9 + i] = c[i];
-            if (o.level_shifts) {
-                o.level_shifts[((int64_t)r * L + l) * 2] = sx;
-                o.level_shifts[((int64_t)r * L + l) * 2 + 1] = sy;
-            }
-            bx = 2 * sx;
-            by = 2 * sy;
-        }
-        o.shifts[2 * r] = sx;
-        o.shifts[2 * r + 1] = sy;
-        o.errs[r] = err;
+        const int p = threadIdx.x;
+        const uint32_t *c = tot + p * 9;
+        const int32_t *bases = pair_bases(a, p);
+        const int bx = (int32_t)load_shared((const uint32_t *)bases);
+        const int by = (int32_t)load_shared((const uint32_t *)bases + 1);
+        const int best = argmin9(c);
+        write_level(a, p, 0, c, bx + best % 3 - 1, by + best / 3 - 1);
     }
 }
 
@@ -791,14 +830,17 @@ __device__ void finalize(const SearchArgs &a)
 //
 // Ordering without device-wide fences (which on gfx950 write back the whole
 // L2): everything workgroups exchange within a launch is written and read
-// with agent-scope atomics, performed at the coherence point.  The workgroup
-// barrier waits until this workgroup's atomics have completed before thread 0
-// takes its ticket, and each ticket counter is a single agent-scope atomic,
-// so the workgroup that draws the last ticket observes every other
-// workgroup's completed writes.
+// with agent-scope atomics, performed at the coherence point.  Every thread
+// first waits until its own memory operations have been acknowledged
+// (vmcnt 0: stores and atomics performed), then the workgroup barrier, and
+// only then does thread 0 take its ticket; each ticket counter is a single
+// agent-scope atomic, so the workgroup that draws the last ticket observes
+// every other workgroup's completed writes.  (A workgroup barrier alone does
+// not wait for outstanding global writes.)
 __device__ bool last_workgroup(uint32_t *t)
 {
     __shared__ int s_last;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t n = gridDim.x * gridDim.y;
@@ -941,18 +983,19 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx)
                     c[(dy + 1) * 3 + dx + 1] = w[(by + dy + RR) * side + (bx + dx + RR)];
-            for (int q = 0; q < 9; ++q)
-                store_shared(state + l * kCounterWords + q, c[q]);  // copy 0 holds the total
-            store_shared((uint32_t *)bases + 2 * l, (uint32_t)bx);
-            store_shared((uint32_t *)bases + 2 * l + 1, (uint32_t)by);
+            if (l == g.L - a.coarse_n && l > 0) {
+                // The first fine level starts from these: copy 0 holds the total.
+                for (int q = 0; q < 9; ++q)
+                    store_shared(state + l * kCounterWords + q, c[q]);
+                store_shared((uint32_t *)bases + 2 * l, (uint32_t)bx);
+                store_shared((uint32_t *)bases + 2 * l + 1, (uint32_t)by);
+            }
             const int best = argmin9(c);
-            bx = 2 * (bx + best % 3 - 1);
-            by = 2 * (by + best / 3 - 1);
+            const int sx = bx + best % 3 - 1, sy = by + best / 3 - 1;
+            write_level(a, p, l, c, sx, sy);
+            bx = 2 * sx;
+            by = 2 * sy;
         }
-    }
-    if (a.coarse_n == g.L) {
-        __syncthreads();
-        finalize(a);
     }
 }
 
@@ -987,17 +1030,24 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
                 c[i] = s;
             }
             const int best = argmin9(c);
-            sbase[0] = 2 * (sprev[0] + best % 3 - 1);
-            sbase[1] = 2 * (sprev[1] + best / 3 - 1);
+            const int sx = sprev[0] + best % 3 - 1, sy = sprev[1] + best / 3 - 1;
+            sbase[0] = 2 * sx;
+            sbase[1] = 2 * sy;
             if (blockIdx.x == 0) {
-                bases[2 * l] = sbase[0];
-                bases[2 * l + 1] = sbase[1];
+                // Read by the next level's launch, or by this launch's last
+                // workgroup at level 0.
+                store_shared((uint32_t *)bases + 2 * l, (uint32_t)sbase[0]);
+                store_shared((uint32_t *)bases + 2 * l + 1, (uint32_t)sbase[1]);
+                if (l + 1 < g.L - a.coarse_n)
+                    write_level(a, pair, l + 1, c, sx, sy);
             }
         }
     } else if (threadIdx.x == 0) {
         sbase[0] = sbase[1] = 0;
-        if (blockIdx.x == 0)
-            bases[2 * l] = bases[2 * l + 1] = 0;
+        if (blockIdx.x == 0) {
+            store_shared((uint32_t *)bases + 2 * l, 0u);
+            store_shared((uint32_t *)bases + 2 * l + 1, 0u);
+        }
     }
     __syncthreads();
 
@@ -1022,7 +1072,7 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
             atomicAdd(state + l * kCounterWords + (blockIdx.x % kCopies) * 9 + threadIdx.x, s);
     }
     if (l == 0 && last_workgroup(a.done + kTicketGroups + 1))
-        finalize(a);
+        finalize_level0(a);
 }
 
 }  // namespace

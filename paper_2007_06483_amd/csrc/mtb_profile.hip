@@ -25,20 +25,52 @@ thread_local char t_filter[48] = {0};  // empty: every kernel
 thread_local std::vector<Record> t_records;
 thread_local hipError_t t_error = hipSuccess;
 
+// Events are reused across profiling sessions: creating one per launch costs
+// enough host time to starve the GPU between short kernels.  Kept per device.
+struct PooledEvent {
+    int device;
+    hipEvent_t event;
+};
+thread_local std::vector<PooledEvent> t_pool;
+
+hipEvent_t take_event(hipError_t *err)
+{
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess)
+        return nullptr;
+    for (size_t i = t_pool.size(); i-- > 0;) {
+        if (t_pool[i].device == dev) {
+            hipEvent_t e = t_pool[i].event;
+            t_pool.erase(t_pool.begin() + i);
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    *err = hipEventCreate(&e);
+    return *err == hipSuccess ? e : nullptr;
+}
+
+void give_event(hipEvent_t e)
+{
+    int dev = 0;
+    if (e && hipGetDevice(&dev) == hipSuccess)
+        t_pool.push_back(PooledEvent{dev, e});
+}
+
 }  // namespace
 
 ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), stream_(s), start_(nullptr)
 {
     if (!t_enabled || (t_filter[0] && strcmp(t_filter, name) != 0))
         return;
-    hipEvent_t e = nullptr;
-    hipError_t r = hipEventCreate(&e);
+    hipError_t r = hipSuccess;
+    hipEvent_t e = take_event(&r);
     if (r == hipSuccess)
         r = hipEventRecord(e, s);
     if (r != hipSuccess) {
         t_error = r;
-        if (e)
-            (void)hipEventDestroy(e);
+        give_event(e);
         return;
     }
     start_ = e;
@@ -48,15 +80,14 @@ ProfScope::~ProfScope()
 {
     if (!t_enabled || !start_)
         return;
-    hipEvent_t e = nullptr;
-    hipError_t r = hipEventCreate(&e);
+    hipError_t r = hipSuccess;
+    hipEvent_t e = take_event(&r);
     if (r == hipSuccess)
         r = hipEventRecord(e, stream_);
     if (r != hipSuccess) {
         t_error = r;
-        if (e)
-            (void)hipEventDestroy(e);
-        (void)hipEventDestroy((hipEvent_t)start_);
+        give_event(e);
+        give_event((hipEvent_t)start_);
         return;
     }
     t_records.push_back(Record{name_, (hipEvent_t)start_, e});
@@ -92,8 +123,8 @@ mtb_status mtb_profile_end(mtb_kernel_time *h_out, int32_t capacity, int32_t *h_
         float ms = 0.f;
         if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
             status = MTB_ERR_DEVICE;
-        (void)hipEventDestroy(r.start);
-        (void)hipEventDestroy(r.stop);
+        give_event(r.start);
+        give_event(r.stop);
         int32_t i = 0;
         while (i < count && strcmp(h_out[i].name, r.name) != 0)
             ++i;
