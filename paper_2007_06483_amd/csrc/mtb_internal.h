@@ -2,6 +2,7 @@
 // HIP kernels (mtb_kernels.hip) and the C-ABI entry points (mtb_api.hip).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -136,20 +137,26 @@ struct ZeroArgs {
     int32_t count;
 };
 
-// Brackets one kernel launch with timing events when profiling is on
-// (mtb_profile_begin); otherwise does nothing.
-class ProfScope {
-  public:
-    ProfScope(const char *name, hipStream_t s);
-    ~ProfScope();
-    ProfScope(const ProfScope &) = delete;
-    ProfScope &operator=(const ProfScope &) = delete;
-
-  private:
-    const char *name_;
-    hipStream_t stream_;
-    void *start_;
+// Timing events for one launch of kernel `name`: both null unless profiling
+// is on for that name (mtb_profile_begin).  The launch carries them in its
+// own dispatch, so timing adds no work to the stream between kernels.
+struct ProfEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
 };
+ProfEvents prof_take(const char *name);
+// Files the events of a launch that returned `launched` (or recycles them).
+void prof_commit(const char *name, const ProfEvents &ev, hipError_t launched);
+
+// Launches k<<<grid, block, 0, s>>>(a), timed when profiling is on.
+template <typename A>
+hipError_t launch_kernel(const char *name, void (*k)(A), dim3 grid, dim3 block, hipStream_t s, A a)
+{
+    const ProfEvents ev = prof_take(name);
+    void *args[] = {&a};
+    const hipError_t e = hipExtLaunchKernel((const void *)k, grid, block, args, 0, s, ev.start, ev.stop, 0);
+    prof_commit(name, ev, e);
+    return e;
+}
 
 // Launch helpers (mtb_kernels.hip).  Each returns the hipError_t of its launches.
 hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);

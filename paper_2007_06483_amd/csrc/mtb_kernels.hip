@@ -1088,11 +1088,7 @@ hipError_t launch_zero(const ZeroArgs &a, hipStream_t s)
         most = a.words[i] > most ? a.words[i] : most;
     int blocks = (int)((most + 255) / 256);
     blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
-    {
-        ProfScope prof_("k_zero", s);
-        hipLaunchKernelGGL(k_zero, dim3(blocks, a.count), dim3(256), 0, s, a);
-    }
-    return hipGetLastError();
+    return launch_kernel("k_zero", k_zero, dim3(blocks, a.count), dim3(256), s, a);
 }
 
 hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
@@ -1107,11 +1103,7 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     per = per < 1 ? 1 : per;
     a.tiles_per_block = (int32_t)per;
     const int blocks = (int)((total + per - 1) / per);
-    {
-        ProfScope prof_("k_pyramid", s);
-        hipLaunchKernelGGL(k_pyramid, dim3(blocks), dim3(256), 0, s, a);
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_kernel("k_pyramid", k_pyramid, dim3(blocks), dim3(256), s, a);
     if (e != hipSuccess || a.g.L <= kFused)
         return e;
     CoarsePyramidArgs c;
@@ -1120,11 +1112,7 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     c.n = a.n;
     c.pad_ = 0;
     c.g = a.g;
-    {
-        ProfScope prof_("k_pyramid_coarse", s);
-        hipLaunchKernelGGL(k_pyramid_coarse, dim3(a.n), dim3(256), 0, s, c);
-    }
-    return hipGetLastError();
+    return launch_kernel("k_pyramid_coarse", k_pyramid_coarse, dim3(a.n), dim3(256), s, c);
 }
 
 hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
@@ -1133,11 +1121,7 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
     int64_t blocks = (total + 3) / 4;
     const int64_t cap = (int64_t)cus * 8;
     blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
-    {
-        ProfScope prof_("k_bitmaps", s);
-        hipLaunchKernelGGL(k_bitmaps, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    }
-    return hipGetLastError();
+    return launch_kernel("k_bitmaps", k_bitmaps, dim3((unsigned)blocks), dim3(256), s, a);
 }
 
 // The i-th coarsest level is searched exhaustively when i < kCoarseLevels and
@@ -1156,11 +1140,7 @@ hipError_t launch_search(SearchArgs a, int cus, hipStream_t s)
         int items = 0;
         for (int i = 0; i < cn; ++i)
             items += (2 * coarse_radius(i) + 1) * coarse_slabs(g.lv[g.L - 1 - i]);
-        {
-            ProfScope prof_("k_search_coarse", s);
-            hipLaunchKernelGGL(k_search_coarse, dim3(items, a.npairs), dim3(256), 0, s, a);
-        }
-        e = hipGetLastError();
+        e = launch_kernel("k_search_coarse", k_search_coarse, dim3(items, a.npairs), dim3(256), s, a);
         if (e != hipSuccess)
             return e;
     }
@@ -1174,11 +1154,7 @@ hipError_t launch_search(SearchArgs a, int cus, hipStream_t s)
         a.level = l;
         a.rows_per_stream = rows;
         const int blocks = (plan_level(g.lv[l], rows).units + 3) / 4;
-        {
-            ProfScope prof_("k_search_fine", s);
-            hipLaunchKernelGGL(k_search_fine, dim3(blocks, a.npairs), dim3(256), 0, s, a);
-        }
-        e = hipGetLastError();
+        e = launch_kernel("k_search_fine", k_search_fine, dim3(blocks, a.npairs), dim3(256), s, a);
         if (e != hipSuccess)
             return e;
     }

@@ -1,10 +1,11 @@
 // mtb_profile.hip -- optional per-kernel timing with HIP events.
 //
 // While a thread has profiling switched on (mtb_profile_begin), every kernel
-// the library launches from that thread is bracketed by two events recorded
-// on the launch stream; mtb_profile_end waits for them and reports the total
-// time per kernel name.  Switched off (the default), a launch costs one
-// thread-local flag test.
+// the library launches from that thread carries a start and a stop event in
+// its own dispatch (hipExtLaunchKernel), so no marker is queued between
+// kernels; mtb_profile_end waits for them and reports the total time per
+// kernel name.  Switched off (the default), a launch costs one thread-local
+// flag test.
 
 #include <string.h>
 
@@ -47,7 +48,8 @@ hipEvent_t take_event(hipError_t *err)
         }
     }
     hipEvent_t e = nullptr;
-    *err = hipEventCreate(&e);
+    // Timing only: no system-scope fence (cache writeback) when the event completes.
+    *err = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return *err == hipSuccess ? e : nullptr;
 }
 
@@ -60,37 +62,34 @@ void give_event(hipEvent_t e)
 
 }  // namespace
 
-ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), stream_(s), start_(nullptr)
+ProfEvents prof_take(const char *name)
 {
+    ProfEvents ev;
     if (!t_enabled || (t_filter[0] && strcmp(t_filter, name) != 0))
-        return;
+        return ev;
     hipError_t r = hipSuccess;
-    hipEvent_t e = take_event(&r);
+    ev.start = take_event(&r);
     if (r == hipSuccess)
-        r = hipEventRecord(e, s);
+        ev.stop = take_event(&r);
     if (r != hipSuccess) {
         t_error = r;
-        give_event(e);
-        return;
+        give_event(ev.start);
+        give_event(ev.stop);
+        return ProfEvents();
     }
-    start_ = e;
+    return ev;
 }
 
-ProfScope::~ProfScope()
+void prof_commit(const char *name, const ProfEvents &ev, hipError_t launched)
 {
-    if (!t_enabled || !start_)
+    if (!ev.start)
         return;
-    hipError_t r = hipSuccess;
-    hipEvent_t e = take_event(&r);
-    if (r == hipSuccess)
-        r = hipEventRecord(e, stream_);
-    if (r != hipSuccess) {
-        t_error = r;
-        give_event(e);
-        give_event((hipEvent_t)start_);
+    if (launched != hipSuccess) {
+        give_event(ev.start);
+        give_event(ev.stop);
         return;
     }
-    t_records.push_back(Record{name_, (hipEvent_t)start_, e});
+    t_records.push_back(Record{name, ev.start, ev.stop});
 }
 
 }  // namespace mtb
