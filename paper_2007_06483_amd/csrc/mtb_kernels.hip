@@ -17,6 +17,8 @@ namespace mtb {
 namespace {
 
 constexpr int kWave = 64;
+// Rows per batch of the fine search (rows per stream is a multiple of it).
+constexpr int kSearchBatch = 2;
 
 // Index of the calling wavefront in its workgroup, as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -543,32 +545,20 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh
     return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
 
-// Loads row words q .. q+2 of row j of a plane (zero outside the row and outside the level).
-__device__ __forceinline__ void load3(const uint32_t *plane, int j, int h, int n32, int q, uint32_t *w)
-{
-    w[0] = w[1] = w[2] = 0u;
-    if (j >= 0 && j < h) {
-        const uint32_t *p = plane + j * n32;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            if (q + i >= 0 && q + i < n32)
-                w[i] = p[q + i];
-    }
-}
-
-// One batch of four reference rows of a work unit and, for each, the moving
-// row one below it (ddy = -1): kW words of each moving row around the lane's
-// column (see search_unit_t).
-template <int kW>
+// One batch of kB reference rows of a work unit and, for each, the moving row
+// one below it (ddy = -1): the lane's two reference words and kW words of the
+// moving row around them (see search_unit_t).
+template <int kB, int kW>
 struct RowBatch {
-    uint32_t rt[4], re[4], mt[4][kW], me[4][kW];
+    uint2 rt[kB], re[kB];
+    uint32_t mt[kB][kW], me[kB][kW];
 };
 
 // The three horizontally shifted copies (ddx = -1, 0, +1 -> index 0, 1, 2) of
 // one 32-pixel word k of a moving bitmap row: bits [t, t+32) of the row with
 // t = 32k - (bx + ddx), from the row words m[0], m[1] (and m[2]) starting at
 // word floor((32k - bx - 1) / 32); r = (32k - bx - 1) mod 32 (wave-uniform).
-// kCase 0: r <= 29; kCase 1: r == 30; kCase 2: r == 31 (only this one needs m2).
+// kCase 0: r <= 29; kCase 1: r == 30; kCase 2: r == 31 (only this one needs m[2]).
 template <int kCase>
 __device__ __forceinline__ void shift3c(const uint32_t *m, uint32_t r, uint32_t *s)
 {
@@ -585,115 +575,169 @@ __device__ __forceinline__ void shift3c(const uint32_t *m, uint32_t r, uint32_t 
     }
 }
 
+// Lanes of one row stream (CW = 2^cw_log2, each lane two words), units across
+// a row and work units of a level, for `rows` rows per stream.
+struct UnitPlan {
+    int cw_log2, units_x, units;
+};
+__host__ __device__ __forceinline__ UnitPlan plan_level(const LevelGeom &lv, int rows)
+{
+    const int cols = lv.wpr;  // two-word columns per row (n32 / 2)
+    // The stream width (8 .. 64 lanes) that pads the row least; ties go wide.
+    int best = 6, best_pad = 1 << 30;
+    for (int c = 6; c >= 3; --c) {
+        const int pad = (((cols + (1 << c) - 1) >> c) << c) - cols;
+        if (pad < best_pad) {
+            best = c;
+            best_pad = pad;
+        }
+    }
+    UnitPlan p;
+    p.cw_log2 = best;
+    p.units_x = (cols + (1 << best) - 1) >> best;
+    const int rows_per_unit = rows * (kWave >> best);
+    p.units = p.units_x * ((lv.h + rows_per_unit - 1) / rows_per_unit);
+    return p;
+}
+
 // Nine candidate errors of one work unit.  A wavefront covers CW = 2^cw_log2
-// dword columns and 64 / CW row streams; each stream walks `rows` rows, four
-// at a time, with the next batch's loads in flight while one batch is scored.
-// Loads never branch: row and column indices are clamped into the level and
-// the exclusion words of anything outside it are masked to zero, which zeroes
+// lanes of two dword columns each and 64 / CW row streams; each stream walks
+// `rows` rows (a multiple of kB, the same for every stream), kB at a time,
+// with the next batch's loads in flight while one batch is scored.  Loads
+// never branch: row and column indices are clamped into the level, and the
+// exclusion words of anything outside it are masked to zero when the batch is
+// scored (not when it is loaded, which would wait for the loads), zeroing
 // those pixels' contribution whatever their threshold bits hold.
 template <int kCase>
 __device__ void search_unit_t(const uint8_t *ref, const uint8_t *mov, const LevelGeom &lv, int bx, int by,
                               int unit, int cw_log2, int rows, int units_x, uint32_t acc[9])
 {
-    constexpr int kW = kCase == 2 ? 3 : 2;  // moving words needed per row
+    constexpr int kB = kSearchBatch;        // rows per batch
+    constexpr int kW = kCase == 2 ? 4 : 3;  // moving words per row for two reference words
+    constexpr int kG = kW - 1;              // words the window may start before the row
     const int lane = threadIdx.x & 63;
     const int n32 = 2 * lv.wpr;
     const int h = lv.h;
     const int sx = unit % units_x, sy = unit / units_x;
-    const int k = (sx << cw_log2) + (lane & ((1 << cw_log2) - 1));
+    const int k = 2 * ((sx << cw_log2) + (lane & ((1 << cw_log2) - 1)));  // first of the lane's two words
     const int stream = lane >> cw_log2;
     const int y_begin = (sy * (kWave >> cw_log2) + stream) * rows;
-    const int y_end = y_begin + rows < h ? y_begin + rows : h;
-    if (y_begin >= h)
-        return;
+    const int y_end = y_begin + rows < h ? y_begin + rows : h;  // y_end - 1 is a row of the level
     const uint8_t *tr = ref + lv.tb_off, *er = ref + lv.eb_off;
-    const uint8_t *tm = mov + lv.tb_off, *em = mov + lv.eb_off;
     const int u = -bx - 1;
     const int q = k + (u >> 5);  // arithmetic shift: floor((-bx - 1) / 32)
     const uint32_t r = (uint32_t)u & 31u;
     const int row_bytes = 4 * n32;
 
-    // Per-lane column window and validity masks, fixed for the unit.  The
-    // window's first word qc is q clamped to [-2, n32 - 1]; where that moves
-    // it, every word of the window is outside the row and masked.  Its words
-    // then lie within two words of the row, which the layout keeps inside the
-    // buffer (a 256-byte guard precedes the first plane, the medians follow
-    // the last): tm8/em8 point 8 bytes before the planes so offsets stay >= 0.
-    const uint32_t kref = 4u * (uint32_t)(k < n32 ? k : n32 - 1);
-    const uint32_t ref_ok = k < n32 ? ~0u : 0u;
-    const int qc = q < -2 ? -2 : (q > n32 - 1 ? n32 - 1 : q);
-    const uint32_t coff = 4u * (uint32_t)(qc + 2);
+    // Per-lane column window and validity masks, fixed for the unit.  n32 is
+    // even, so both reference words are in the row or neither is.  Where the
+    // window q .. q+kW-1 lies wholly outside the row its start is clamped to
+    // [-kG, n32 - 1] (every word stays masked); its words then lie within kG
+    // words of the row, which the layout keeps inside the buffer (a 256-byte
+    // guard precedes the first plane, the medians follow the last); tmg/emg
+    // point kG words before the planes so offsets stay >= 0.
+    const uint32_t kref = 4u * (uint32_t)(k < n32 ? k : n32 - 2);
+    const uint32_t ref_ok = (k < n32 && y_begin < h) ? ~0u : 0u;
+    const int qc = q < -kG ? -kG : (q > n32 - 1 ? n32 - 1 : q);
+    const uint32_t coff = 4u * (uint32_t)(qc + kG);
     uint32_t cmask[kW];
 #pragma unroll
     for (int i = 0; i < kW; ++i)
         cmask[i] = (q + i >= 0 && q + i < n32) ? ~0u : 0u;
-    const uint8_t *tm8 = tm - 8, *em8 = em - 8;
+    const uint8_t *tmg = mov + lv.tb_off - 4 * kG, *emg = mov + lv.eb_off - 4 * kG;
     auto load_moving = [&](int j, uint32_t *wt, uint32_t *we) {
         const int jc = j < 0 ? 0 : (j >= h ? h - 1 : j);
-        const uint32_t rmask = j == jc ? ~0u : 0u;
         const uint32_t off = (uint32_t)jc * (uint32_t)row_bytes + coff;
 #pragma unroll
         for (int i = 0; i < kW; ++i) {
-            wt[i] = *(const uint32_t *)(tm8 + off + 4 * i);
-            we[i] = *(const uint32_t *)(em8 + off + 4 * i) & cmask[i] & rmask;
+            wt[i] = *(const uint32_t *)(tmg + off + 4 * i);
+            we[i] = *(const uint32_t *)(emg + off + 4 * i);
         }
     };
-    auto load = [&](int y, RowBatch<kW> &b) {
+    // Exclusion words of moving row j with everything outside the level cleared.
+    auto mask_moving = [&](int j, const uint32_t *we, uint32_t *out) {
+        const uint32_t rmask = (uint32_t)j < (uint32_t)h ? ~0u : 0u;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kW; ++i)
+            out[i] = we[i] & cmask[i] & rmask;
+    };
+    auto load = [&](int y, RowBatch<kB, kW> &b) {
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
             const int yy = y + i < y_end ? y + i : y_end - 1;
-            const uint32_t ok = y + i < y_end ? ref_ok : 0u;
             const uint32_t base = (uint32_t)yy * (uint32_t)row_bytes + kref;
-            b.rt[i] = *(const uint32_t *)(tr + base);
-            b.re[i] = *(const uint32_t *)(er + base) & ok;
-            load_moving(yy - by + 1, b.mt[i], b.me[i]);
+            b.rt[i] = *(const uint2 *)(tr + base);
+            b.re[i] = *(const uint2 *)(er + base);
+            load_moving(y + i - by + 1, b.mt[i], b.me[i]);
         }
     };
 
-    // Moving rows seen by reference row y: y - by - ddy for ddy = +1, 0, -1.
-    uint32_t at[3], ae[3], bt[3], be[3];
-    auto score = [&](const RowBatch<kW> &b) {
+    // Shifted moving words seen by reference row y: rows y - by - ddy for
+    // ddy = +1 (a*), 0 (b*); [word][ddx].
+    uint32_t at[2][3], ae[2][3], bt[2][3], be[2][3];
+    auto shift_row = [&](const uint32_t *mt, const uint32_t *me, uint32_t (*ct)[3], uint32_t (*ce)[3]) {
+        shift3c<kCase>(mt, r, ct[0]);
+        shift3c<kCase>(mt + 1, r, ct[1]);
+        shift3c<kCase>(me, r, ce[0]);
+        shift3c<kCase>(me + 1, r, ce[1]);
+    };
+    auto score = [&](const RowBatch<kB, kW> &b, int y) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            uint32_t ct[3], ce[3];
-            shift3c<kCase>(b.mt[i], r, ct);
-            shift3c<kCase>(b.me[i], r, ce);
+        for (int i = 0; i < kB; ++i) {
+            const uint32_t ok = y + i < y_end ? ref_ok : 0u;
+            const uint32_t rt[2] = {b.rt[i].x, b.rt[i].y};
+            const uint32_t re[2] = {b.re[i].x & ok, b.re[i].y & ok};
+            uint32_t me[kW], ct[2][3], ce[2][3];
+            mask_moving(y + i - by + 1, b.me[i], me);
+            shift_row(b.mt[i], me, ct, ce);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                acc[d] += __builtin_popcount((b.rt[i] ^ ct[d]) & b.re[i] & ce[d]);      // ddy = -1
-                acc[3 + d] += __builtin_popcount((b.rt[i] ^ bt[d]) & b.re[i] & be[d]);  // ddy = 0
-                acc[6 + d] += __builtin_popcount((b.rt[i] ^ at[d]) & b.re[i] & ae[d]);  // ddy = +1
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    acc[d] += __builtin_popcount((rt[w] ^ ct[w][d]) & re[w] & ce[w][d]);      // ddy = -1
+                    acc[3 + d] += __builtin_popcount((rt[w] ^ bt[w][d]) & re[w] & be[w][d]);  // ddy = 0
+                    acc[6 + d] += __builtin_popcount((rt[w] ^ at[w][d]) & re[w] & ae[w][d]);  // ddy = +1
+                }
             }
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                at[d] = bt[d];
-                ae[d] = be[d];
-                bt[d] = ct[d];
-                be[d] = ce[d];
-            }
+            for (int w = 0; w < 2; ++w)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    at[w][d] = bt[w][d];
+                    ae[w][d] = be[w][d];
+                    bt[w][d] = ct[w][d];
+                    be[w][d] = ce[w][d];
+                }
         }
     };
 
-    RowBatch<kW> b0, b1;
+    RowBatch<kB, kW> b0, b1;
     {
-        uint32_t w[4][kW];
+        uint32_t w[4][kW], m[2][kW];
         load_moving(y_begin - by - 1, w[0], w[1]);
         load_moving(y_begin - by, w[2], w[3]);
         load(y_begin, b0);
-        shift3c<kCase>(w[0], r, at);
-        shift3c<kCase>(w[1], r, ae);
-        shift3c<kCase>(w[2], r, bt);
-        shift3c<kCase>(w[3], r, be);
+        mask_moving(y_begin - by - 1, w[1], m[0]);
+        mask_moving(y_begin - by, w[3], m[1]);
+        shift_row(w[0], m[0], at, ae);
+        shift_row(w[2], m[1], bt, be);
     }
-    for (int y = y_begin; y < y_end; y += 8) {
-        if (y + 4 < y_end)
-            load(y + 4, b1);
-        score(b0);
-        if (y + 4 >= y_end)
+    // Every branch below is uniform (rows is); each batch's loads are issued
+    // in the same block as the scoring of the batch before.
+    for (int i = 0;; i += 2 * kB) {
+        const int y = y_begin + i;
+        if (i + kB >= rows) {
+            score(b0, y);
             break;
-        if (y + 8 < y_end)
-            load(y + 8, b0);
-        score(b1);
+        }
+        load(y + kB, b1);
+        score(b0, y);
+        if (i + 2 * kB >= rows) {
+            score(b1, y + kB);
+            break;
+        }
+        load(y + 2 * kB, b0);
+        score(b1, y + kB);
     }
 }
 
@@ -726,24 +770,6 @@ __device__ __forceinline__ int argmin9(const uint32_t *c)
         if (c[i] < c[best])
             best = i;
     return best;
-}
-
-struct UnitPlan {
-    int cw_log2, units_x, units;
-};
-
-__host__ __device__ __forceinline__ UnitPlan plan_level(const LevelGeom &lv, int rows)
-{
-    const int n32 = 2 * lv.wpr;
-    int cw_log2 = 0;
-    while ((1 << cw_log2) < n32 && cw_log2 < 6)
-        ++cw_log2;
-    UnitPlan p;
-    p.cw_log2 = cw_log2;
-    p.units_x = (n32 + (1 << cw_log2) - 1) >> cw_log2;
-    const int rows_per_unit = rows * (kWave >> cw_log2);
-    p.units = p.units_x * ((lv.h + rows_per_unit - 1) / rows_per_unit);
-    return p;
 }
 
 // Loads and stores of words that several workgroups (on different XCDs) exchange
@@ -875,13 +901,39 @@ __host__ __device__ __forceinline__ int coarse_slabs(const LevelGeom &lv)
     return (lv.h + rows - 1) / rows;
 }
 
+// Walks pair p's coarse error surfaces (in `surf`) from the coarsest level
+// down, testing the same nine candidates in the same order, with the same
+// tie-break, as the nine-candidate search; records each level's outputs when
+// `write` is set.  Returns the shift chosen at the finest coarse level.
+__device__ int2 coarse_walk(const SearchArgs &a, int p, const uint32_t *surf, bool write)
+{
+    int bx = 0, by = 0, sx = 0, sy = 0;
+    for (int i = 0; i < a.coarse_n; ++i) {
+        const int R = coarse_radius(i), side = 2 * R + 1;
+        const uint32_t *w = surf + coarse_surface_offset(i);
+        uint32_t c[9];
+        // |bx|, |by| <= 2^(i+1) - 2 here, so every candidate lies in the window.
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                c[(dy + 1) * 3 + dx + 1] = w[(by + dy + R) * side + (bx + dx + R)];
+        const int best = argmin9(c);
+        sx = bx + best % 3 - 1;
+        sy = by + best / 3 - 1;
+        if (write)
+            write_level(a, p, a.g.L - 1 - i, c, sx, sy);
+        bx = 2 * sx;
+        by = 2 * sy;
+    }
+    return make_int2(sx, sy);
+}
+
 // Exhaustive search of the coarse levels.  The i-th coarsest level (i <
 // coarse_n) is searched over every shift within radius R = 2^(i+1) - 1, which
 // holds every candidate the coarse-to-fine search can test there.  Workgroup
 // (item, pair) adds the errors of one row of a level's window (cy fixed,
-// cx = -R..R) over one slab of rows into the pair's error surface; the last
-// workgroup to finish walks the windows coarse to fine exactly as the
-// nine-candidate search would, recording each level's nine errors and base.
+// cx = -R..R) over one slab of rows into the pair's error surface.  The first
+// fine level walks the surfaces; when every level is coarse, the last
+// workgroup to finish walks them here and writes the outputs.
 __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
 {
     constexpr int kMaxR = 7;
@@ -906,10 +958,11 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
     const int cy = item / slabs - R;
     const int y_lo = (item % slabs) * coarse_slab_rows(lv);
     const int n32 = 2 * lv.wpr, h = lv.h;
-    const uint32_t *tr = (const uint32_t *)(a.ref[pair] + lv.tb_off);
-    const uint32_t *er = (const uint32_t *)(a.ref[pair] + lv.eb_off);
-    const uint32_t *tm = (const uint32_t *)(a.mov[pair] + lv.tb_off);
-    const uint32_t *em = (const uint32_t *)(a.mov[pair] + lv.eb_off);
+    const int row_bytes = 4 * n32;
+    const uint8_t *tr = a.ref[pair] + lv.tb_off, *er = a.ref[pair] + lv.eb_off;
+    // 4 bytes before the planes: column k-1 of row 0 stays inside the buffer
+    // (the bitmap layout keeps a guard before the first plane).
+    const uint8_t *tm4 = a.mov[pair] + lv.tb_off - 4, *em4 = a.mov[pair] + lv.eb_off - 4;
 
     const int cw_log2 = coarse_cw_log2(lv);
     const int cw = 1 << cw_log2;
@@ -921,28 +974,41 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
     for (int c = 0; c < 2 * kMaxR + 1; ++c)
         acc[c] = 0u;
     for (int k = col; k < n32; k += cw) {
+        // Words k-1 .. k+1 of moving row y - cy hold every shift |cx| <= 7 of
+        // word k.  Rows and columns outside the level are read clamped (or
+        // from the neighbouring row) and their exclusion words masked below.
+        const uint32_t cm0 = k >= 1 ? ~0u : 0u, cm2 = k + 1 < n32 ? ~0u : 0u;
         uint32_t t[kRows], e[kRows], mt[kRows][3], me[kRows][3];
 #pragma unroll
         for (int b = 0; b < kRows; ++b) {
             const int y = y_lo + stream + b * streams;
-            const bool ok = y < h;
-            t[b] = ok ? tr[y * n32 + k] : 0u;
-            e[b] = ok ? er[y * n32 + k] : 0u;
-            // Shift cx takes bits [32k - cx, 32k - cx + 32) of moving row y - cy:
-            // words k-1 .. k+1, as |cx| <= 7.
-            load3(tm, ok ? y - cy : -1, h, n32, k - 1, mt[b]);
-            load3(em, ok ? y - cy : -1, h, n32, k - 1, me[b]);
+            const int yc = y < h ? y : h - 1;
+            const uint32_t ro = (uint32_t)yc * (uint32_t)row_bytes + 4u * (uint32_t)k;
+            t[b] = *(const uint32_t *)(tr + ro);
+            e[b] = *(const uint32_t *)(er + ro);
+            const int j = y - cy;
+            const int jc = j < 0 ? 0 : (j >= h ? h - 1 : j);
+            const uint32_t mo = (uint32_t)jc * (uint32_t)row_bytes + 4u * (uint32_t)k;  // word k-1 at tm4 + mo
+#pragma unroll
+            for (int w = 0; w < 3; ++w) {
+                mt[b][w] = *(const uint32_t *)(tm4 + mo + 4 * w);
+                me[b][w] = *(const uint32_t *)(em4 + mo + 4 * w);
+            }
         }
 #pragma unroll
         for (int b = 0; b < kRows; ++b) {
+            const int y = y_lo + stream + b * streams;
+            const uint32_t eb = y < h ? e[b] : 0u;
+            const uint32_t rv = (uint32_t)(y - cy) < (uint32_t)h ? ~0u : 0u;
+            const uint32_t m0 = me[b][0] & cm0 & rv, m1 = me[b][1] & rv, m2 = me[b][2] & cm2 & rv;
 #pragma unroll
             for (int c = 0; c < 2 * kMaxR + 1; ++c) {
                 const int cx = c - kMaxR;
                 if (cx >= -R && cx <= R) {
                     const int o = 32 - cx;  // bit offset from the start of word k-1
                     const uint32_t st = o < 32 ? funnel(mt[b][1], mt[b][0], o) : funnel(mt[b][2], mt[b][1], o - 32);
-                    const uint32_t se = o < 32 ? funnel(me[b][1], me[b][0], o) : funnel(me[b][2], me[b][1], o - 32);
-                    acc[c] += __builtin_popcount((t[b] ^ st) & e[b] & se);
+                    const uint32_t se = o < 32 ? funnel(m1, m0, o) : funnel(m2, m1, o - 32);
+                    acc[c] += __builtin_popcount((t[b] ^ st) & eb & se);
                 }
             }
         }
@@ -962,47 +1028,36 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
             atomicAdd(surf + (cy + R) * (2 * R + 1) + threadIdx.x, v);
     }
 
-    if (!last_workgroup(a.done))
+    if (a.coarse_n < g.L || !last_workgroup(a.done))
         return;
-    // Walk the windows: the same candidates, order and tie-break as the
-    // nine-candidate search, for every pair.  All surfaces are fetched at once.
+    // Every level is coarse: walk all pairs' surfaces, fetched at once.
+    constexpr int kLoads = 8;
     __shared__ uint32_t ssurf[kMaxStack * kSurfWords];
-    for (int q = threadIdx.x; q < a.npairs * kSurfWords; q += blockDim.x)
-        ssurf[q] = load_shared(pair_surface(a, q / kSurfWords) + q % kSurfWords);
-    __syncthreads();
-    if ((int)threadIdx.x < a.npairs) {
-        const int p = threadIdx.x;
-        uint32_t *state = pair_state(a, p);
-        int32_t *bases = pair_bases(a, p);
-        const uint32_t *sp = ssurf + p * kSurfWords;
-        int bx = 0, by = 0;
-        for (int ii = 0; ii < a.coarse_n; ++ii) {
-            const int l = g.L - 1 - ii, RR = coarse_radius(ii), side = 2 * RR + 1;
-            const uint32_t *w = sp + coarse_surface_offset(ii);
-            uint32_t c[9];
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx)
-                    c[(dy + 1) * 3 + dx + 1] = w[(by + dy + RR) * side + (bx + dx + RR)];
-            if (l == g.L - a.coarse_n && l > 0) {
-                // The first fine level starts from these: copy 0 holds the total.
-                for (int q = 0; q < 9; ++q)
-                    store_shared(state + l * kCounterWords + q, c[q]);
-                store_shared((uint32_t *)bases + 2 * l, (uint32_t)bx);
-                store_shared((uint32_t *)bases + 2 * l + 1, (uint32_t)by);
-            }
-            const int best = argmin9(c);
-            const int sx = bx + best % 3 - 1, sy = by + best / 3 - 1;
-            write_level(a, p, l, c, sx, sy);
-            bx = 2 * sx;
-            by = 2 * sy;
+    const int words = a.npairs * kSurfWords;
+    for (int q0 = 0; q0 < words; q0 += 256 * kLoads) {
+        uint32_t v[kLoads];
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int q = q0 + u * 256 + (int)threadIdx.x;
+            v[u] = q < words ? load_shared(pair_surface(a, q / kSurfWords) + q % kSurfWords) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int q = q0 + u * 256 + (int)threadIdx.x;
+            if (q < words)
+                ssurf[q] = v[u];
         }
     }
+    __syncthreads();
+    if ((int)threadIdx.x < a.npairs)
+        coarse_walk(a, threadIdx.x, ssurf + threadIdx.x * kSurfWords, true);
 }
 
 // One level below the coarse ones, for every pair: grid (workgroups per pair, pairs).
 __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
 {
-    __shared__ uint32_t cnt[kCounterWords];
+    __shared__ uint32_t cnt[kSurfWords > kCounterWords ? kSurfWords : kCounterWords];
+    __shared__ uint32_t tot[9];
     __shared__ int sprev[2];
     __shared__ int sbase[2];
     __shared__ uint32_t red[4][9];
@@ -1015,41 +1070,65 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
     int32_t *bases = pair_bases(a, pair);
 
     // Base of this level = twice the winner of the level above (one round trip).
-    if (l < g.L - 1) {
+    if (a.coarse_n > 0 && l == g.L - 1 - a.coarse_n) {
+        // First level after the coarse ones: walk their surfaces.
+        const uint32_t *surf = pair_surface(a, pair);
+        uint32_t v[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int q = u * 256 + (int)threadIdx.x;
+            v[u] = q < kSurfWords ? surf[q] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int q = u * 256 + (int)threadIdx.x;
+            if (q < kSurfWords)
+                cnt[q] = v[u];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int2 s = coarse_walk(a, pair, cnt, blockIdx.x == 0);
+            sbase[0] = 2 * s.x;
+            sbase[1] = 2 * s.y;
+        }
+    } else if (l < g.L - 1) {
         if (threadIdx.x < kCounterWords)
             cnt[threadIdx.x] = state[(l + 1) * kCounterWords + threadIdx.x];
         else if (threadIdx.x < kCounterWords + 2)
             sprev[threadIdx.x - kCounterWords] = bases[2 * (l + 1) + threadIdx.x - kCounterWords];
         __syncthreads();
+        if (threadIdx.x < 9) {
+            uint32_t s = 0;
+#pragma unroll
+            for (int k = 0; k < kCopies; ++k)
+                s += cnt[k * 9 + threadIdx.x];
+            tot[threadIdx.x] = s;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t c[9];
-            for (int i = 0; i < 9; ++i) {
-                uint32_t s = 0;
-                for (int k = 0; k < kCopies; ++k)
-                    s += cnt[k * 9 + i];
-                c[i] = s;
-            }
+            for (int i = 0; i < 9; ++i)
+                c[i] = tot[i];
             const int best = argmin9(c);
             const int sx = sprev[0] + best % 3 - 1, sy = sprev[1] + best / 3 - 1;
             sbase[0] = 2 * sx;
             sbase[1] = 2 * sy;
-            if (blockIdx.x == 0) {
-                // Read by the next level's launch, or by this launch's last
-                // workgroup at level 0.
-                store_shared((uint32_t *)bases + 2 * l, (uint32_t)sbase[0]);
-                store_shared((uint32_t *)bases + 2 * l + 1, (uint32_t)sbase[1]);
-                if (l + 1 < g.L - a.coarse_n)
-                    write_level(a, pair, l + 1, c, sx, sy);
-            }
+            if (blockIdx.x == 0)
+                write_level(a, pair, l + 1, c, sx, sy);
         }
     } else if (threadIdx.x == 0) {
         sbase[0] = sbase[1] = 0;
-        if (blockIdx.x == 0) {
-            store_shared((uint32_t *)bases + 2 * l, 0u);
-            store_shared((uint32_t *)bases + 2 * l + 1, 0u);
-        }
     }
     __syncthreads();
+    if (threadIdx.x == 0 && blockIdx.x == 0 && l > 0) {
+        // Read by the next level's launch.
+        bases[2 * l] = sbase[0];
+        bases[2 * l + 1] = sbase[1];
+    } else if (threadIdx.x == 0 && blockIdx.x == 0) {
+        // Read by this launch's last workgroup: published before its ticket.
+        store_shared((uint32_t *)bases, (uint32_t)sbase[0]);
+        store_shared((uint32_t *)bases + 1, (uint32_t)sbase[1]);
+    }
 
     const LevelGeom &lv = g.lv[l];
     const UnitPlan p = plan_level(lv, a.rows_per_stream);
