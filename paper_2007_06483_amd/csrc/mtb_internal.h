@@ -60,7 +60,7 @@ struct PyramidArgs {
     int64_t stride;          // bytes between RGB rows
     int32_t n;               // images
     int32_t tiles_x, tiles_y;
-    int32_t tiles_per_block; // contiguous tiles handled by one workgroup
+    int32_t xcd_tiles;       // tiles of each XCD's contiguous share of the work
     int32_t align;           // 16, 4 or 1: alignment every RGB row start is known to have
     int32_t pad_;
     Geometry g;

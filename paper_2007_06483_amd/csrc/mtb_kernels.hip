@@ -17,6 +17,8 @@ namespace mtb {
 namespace {
 
 constexpr int kWave = 64;
+// Accelerator complex dies (XCDs) of the device, each with its own L2.
+constexpr int kXcds = 8;
 // Rows per batch of the fine search (rows per stream is a multiple of it).
 constexpr int kSearchBatch = 2;
 
@@ -118,8 +120,16 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
 
     const int64_t per_image = (int64_t)a.tiles_x * a.tiles_y;
     const int64_t total = per_image * a.n;
-    const int64_t t0 = (int64_t)blockIdx.x * a.tiles_per_block;
-    const int64_t t1 = t0 + a.tiles_per_block < total ? t0 + a.tiles_per_block : total;
+    // XCD-aware schedule.  Workgroups are dealt to the XCDs in turn, so
+    // workgroup b runs on XCD b % kXcds, and each XCD takes a contiguous share
+    // of the tiles (image-major, then row bands, then columns).  Its slots walk
+    // that share in step, slot s taking tiles s, s + slots, ...: neighbouring
+    // tiles of a row band are read at the same time on the same XCD, so the
+    // cache line two of them share is fetched from HBM once.
+    const int slot = blockIdx.x / kXcds, slots = gridDim.x / kXcds;
+    const int64_t xb = (int64_t)(blockIdx.x % kXcds) * a.xcd_tiles;
+    const int64_t t0 = xb + slot;
+    const int64_t t1 = xb + a.xcd_tiles < total ? xb + a.xcd_tiles : total;
 
     auto flush = [&](int img) {
         __syncthreads();
@@ -164,7 +174,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
 
     int cur = -1;
     int parity = 0;
-    for (int64_t t = t0; t < t1; ++t) {
+    for (int64_t t = t0; t < t1; t += slots) {
         int img, X0, Y0;
         locate(t, img, X0, Y0);
         if (img != cur) {
@@ -215,9 +225,9 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
             }
         }
         // ---- prefetch the next tile's RGB while this one is processed
-        if (fast16 && t + 1 < t1) {
+        if (fast16 && t + slots < t1) {
             int img2, X2, Y2;
-            locate(t + 1, img2, X2, Y2);
+            locate(t + slots, img2, X2, Y2);
             const int x2 = X2 + 16 * bx;
             if (x2 + 15 < g.W)
                 load_rgb16(a.rgb[img2], a.stride, x2, Y2 + 16 * wave + 4 * by, g.H, q);
@@ -1176,12 +1186,13 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     a.tiles_x = (a.g.W + kTileW - 1) / kTileW;
     a.tiles_y = (a.g.H + kTileH - 1) / kTileH;
     const int64_t total = (int64_t)a.tiles_x * a.tiles_y * a.n;
-    // Three workgroups fit on a compute unit at this kernel's register count.
-    const int64_t want = (int64_t)cus * 3;
-    int64_t per = (total + want - 1) / want;
-    per = per < 1 ? 1 : per;
-    a.tiles_per_block = (int32_t)per;
-    const int blocks = (int)((total + per - 1) / per);
+    // Three workgroups fit on a compute unit at this kernel's register count;
+    // each XCD gets the same number of slots (see k_pyramid).
+    const int64_t share = (total + kXcds - 1) / kXcds;
+    int64_t slots = (int64_t)cus * 3 / kXcds;
+    slots = slots > share ? share : (slots < 1 ? 1 : slots);
+    a.xcd_tiles = (int32_t)share;
+    const int blocks = (int)(slots * kXcds);
     hipError_t e = launch_kernel("k_pyramid", k_pyramid, dim3(blocks), dim3(256), s, a);
     if (e != hipSuccess || a.g.L <= kFused)
         return e;
@@ -1223,16 +1234,22 @@ hipError_t launch_search(SearchArgs a, int cus, hipStream_t s)
         if (e != hipSuccess)
             return e;
     }
+    // Workgroups are dealt to the XCDs in turn, so with a row of blocks whose
+    // length is a multiple of kXcds every pair's workgroup for one unit runs
+    // on the same XCD, whose L2 then serves the shared reference rows.
+    auto row_blocks = [&](int l, int rows) {
+        return ((plan_level(g.lv[l], rows).units + 3) / 4 + kXcds - 1) / kXcds * kXcds;
+    };
     for (int l = g.L - 1 - cn; l >= 0; --l) {
         // Rows per stream: the fewest (at least 4) that keep the grid within one
         // round of resident workgroups (three per compute unit at this kernel's
         // register count), so no workgroup waits for another to finish.
         int rows = 4;
-        while (rows < 64 && (int64_t)(plan_level(g.lv[l], rows).units + 3) / 4 * a.npairs > (int64_t)cus * 3)
+        while (rows < 64 && (int64_t)row_blocks(l, rows) * a.npairs > (int64_t)cus * 3)
             rows <<= 1;
         a.level = l;
         a.rows_per_stream = rows;
-        const int blocks = (plan_level(g.lv[l], rows).units + 3) / 4;
+        const int blocks = row_blocks(l, rows);
         e = launch_kernel("k_search_fine", k_search_fine, dim3(blocks, a.npairs), dim3(256), s, a);
         if (e != hipSuccess)
             return e;
