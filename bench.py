@@ -109,13 +109,122 @@ def cpu_baseline(imgs, levels, ref, mp_total, max_threads, min_seconds):
     }
 
 
+def pyramid_bytes(W, H, L):
+    """Algorithmic bytes of one image in k_pyramid: RGB read + every gray level written."""
+    return 3 * W * H + sum((W >> l) * (H >> l) for l in range(L))
+
+
+def run_batch(args, mtb, synth, torch, np, dev):
+    """64 pairs of uneven sizes: the batched call, its HIP-graph replay, and the plain
+    per-pair launch sequence (two pyramids, two bitmap passes, one pair search per item)."""
+    log("generating batch64_uneven ...")
+    t0 = time.perf_counter()
+    batch = synth.make_batch(64, 4)
+    log(f"generated in {time.perf_counter() - t0:.1f} s; uploading")
+    pairs = [(torch.from_numpy(r).to(dev), torch.from_numpy(m).to(dev), L) for r, m, _, L in batch]
+    n = len(pairs)
+    mp_total = sum(2 * r.shape[0] * r.shape[1] for r, _, _, _ in batch) / 1e6
+    ws = torch.empty(mtb.mtb_batch_workspace_bytes(pairs), dtype=torch.uint8, device=dev)
+    shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    errs = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def batched():
+        mtb.mtb_align_batch(pairs, workspace=ws, shifts=shifts, errs=errs)
+
+    # Plain path buffers, allocated once.
+    plain = []
+    for (r, m, L), (ref, _, _, _) in zip(pairs, batch):
+        H, W = ref.shape[:2]
+        plain.append(dict(
+            r=r, m=m, L=L, W=W, H=H,
+            pr=torch.empty(mtb.mtb_pyramid_bytes(W, H, L), dtype=torch.uint8, device=dev),
+            pm=torch.empty(mtb.mtb_pyramid_bytes(W, H, L), dtype=torch.uint8, device=dev),
+            br=torch.empty(mtb.mtb_bitmaps_bytes(W, H, L), dtype=torch.uint8, device=dev),
+            bm=torch.empty(mtb.mtb_bitmaps_bytes(W, H, L), dtype=torch.uint8, device=dev),
+            ws=torch.empty(mtb.mtb_pair_workspace_bytes(L), dtype=torch.uint8, device=dev)))
+    pshift = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    perr = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def per_pair():
+        for k, it in enumerate(plain):
+            mtb.mtb_build_pyramid(it["r"], it["L"], pyramid=it["pr"])
+            mtb.mtb_build_pyramid(it["m"], it["L"], pyramid=it["pm"])
+            mtb.mtb_bitmaps(it["pr"], it["W"], it["H"], it["L"], bitmaps=it["br"])
+            mtb.mtb_bitmaps(it["pm"], it["W"], it["H"], it["L"], bitmaps=it["bm"])
+            mtb.mtb_align_pair(it["br"], it["bm"], it["W"], it["H"], it["L"], workspace=it["ws"],
+                               shift=pshift[k], err=perr[k:k + 1])
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / steps
+
+    # Timed region of the headline number: K batched calls, k_pyramid bracketed by events.
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    mtb.mtb_profile_begin("k_pyramid")
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        batched()
+    torch.cuda.synchronize()
+    ms_batched = (time.perf_counter() - t) * 1e3 / args.steps
+    prof = mtb.mtb_profile_end()
+    launches, total_ms = prof["k_pyramid"]
+
+    ms_plain = timed(per_pair, max(1, args.steps // 4), 1)
+    same = bool(torch.equal(pshift, shifts) and torch.equal(perr, errs))
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batched()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched()
+    ms_graph = timed(graph.replay, args.steps, 1)
+
+    pyr_bytes = sum(pyramid_bytes(it["W"], it["H"], it["L"]) * 2 for it in plain)
+    achieved = pyr_bytes * args.steps / (total_ms / 1e3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": round(mp_total / (ms_batched / 1e3), 1),
+        "unit": "MP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "batch64_uneven", "pairs": n, "megapixels_per_step": round(mp_total, 3),
+                   "sizes": sorted({f"{it['W']}x{it['H']}/L{it['L']}" for it in plain})},
+        "roofline": {"bound": "hbm", "kernel": "k_pyramid", "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": None, "launches_per_step": launches // args.steps},
+        "graph_replay": {"ms_per_step": round(ms_graph, 4), "MPps": round(mp_total / (ms_graph / 1e3), 1)},
+        "plain_per_pair": {"ms_per_step": round(ms_plain, 4), "MPps": round(mp_total / (ms_plain / 1e3), 1),
+                           "same_results": same},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stack7_6000x4000",
-                    choices=["stack7_6000x4000", "pair_4096x3072", "pair_512x384"])
+                    choices=["stack7_6000x4000", "pair_4096x3072", "pair_512x384", "batch64_uneven"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -142,6 +251,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     mtb.lib()  # raises if libmtb.so is not built
     dev = torch.device("cuda:0")
+
+    if args.workload == "batch64_uneven":
+        return run_batch(args, mtb, synth, torch, np, dev)
 
     log(f"generating {args.workload} ...")
     t0 = time.perf_counter()

@@ -184,6 +184,45 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
                            uint32_t *d_trace, void *stream);
 
 /*
+ * One item of a batch: a reference and a moving RGB image of the same size
+ * and row stride (see Images above), aligned with `levels` levels.
+ */
+typedef struct mtb_batch_item {
+    const uint8_t *d_ref_rgb;
+    const uint8_t *d_mov_rgb;
+    int64_t row_stride;
+    int32_t width, height;
+    int32_t levels;
+    int32_t reserved; /* must be 0 */
+} mtb_batch_item;
+
+#define MTB_MAX_BATCH 4096 /* items per mtb_align_batch call */
+
+/* Bytes of the workspace mtb_align_batch needs for these items; 0 if the
+ * item list or any item is invalid. */
+size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items);
+
+/*
+ * Many independent pairs of uneven sizes in one call: for every item, the
+ * pairwise alignment of Section III-A (as mtb_align_pair on the items' own
+ * pyramids and bitmaps, built as in mtb_build_pyramid and mtb_bitmaps).
+ * Items of equal width, height, row stride and level count are processed
+ * together, up to 16 pairs (32 images) per launch of each pass; the groups run
+ * one after another on `stream`, reusing the workspace.  The call enqueues a
+ * fixed sequence of kernels (no host synchronisation, no memset), so it can be
+ * captured in a HIP graph and replayed.
+ *   h_items          host array of n_items items (1 .. MTB_MAX_BATCH)
+ *   exclude_range    as for mtb_bitmaps (Ward: 4)
+ *   d_workspace      >= mtb_batch_workspace_bytes(h_items, n_items) bytes
+ *   d_shifts         int32[n_items][2] receives (dx, dy) per item
+ *   d_errs           uint32[n_items] receives each item's level-0 error
+ * Errors: MTB_ERR_INVALID_ARG, MTB_ERR_WORKSPACE, MTB_ERR_DEVICE.
+ */
+mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range,
+                           void *d_workspace, size_t workspace_bytes, int32_t *d_shifts,
+                           uint32_t *d_errs, void *stream);
+
+/*
  * Per-kernel timing for benchmarks.  Between mtb_profile_begin and
  * mtb_profile_end, every kernel that library calls made from the calling
  * thread launch is bracketed by two HIP events recorded on its stream; with

@@ -35,12 +35,15 @@ __all__ = [
     "mtb_bitmaps",
     "mtb_align_pair",
     "mtb_align_stack",
+    "mtb_batch_workspace_bytes",
+    "mtb_align_batch",
     "mtb_profile_begin",
     "mtb_profile_end",
 ]
 
 MTB_MAX_LEVELS = 16
 MTB_MAX_STACK = 32
+MTB_MAX_BATCH = 4096
 
 MTB_OK = 0
 STATUS_NAMES = {0: "MTB_OK", 1: "MTB_ERR_INVALID_ARG", 2: "MTB_ERR_WORKSPACE",
@@ -76,6 +79,13 @@ class _CLayout(ctypes.Structure):
         ("median_offset", ctypes.c_int64),
         ("bitmaps_bytes", ctypes.c_int64),
     ]
+
+
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("d_ref_rgb", ctypes.c_void_p), ("d_mov_rgb", ctypes.c_void_p),
+                ("row_stride", ctypes.c_int64), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _KernelTime(ctypes.Structure):
@@ -135,6 +145,10 @@ def lib():
     L.mtb_align_pair.restype = ctypes.c_int
     L.mtb_align_stack.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, i32, i32, P, sz, P, P, P, P]
     L.mtb_align_stack.restype = ctypes.c_int
+    L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
+    L.mtb_batch_workspace_bytes.restype = sz
+    L.mtb_align_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P]
+    L.mtb_align_batch.restype = ctypes.c_int
     L.mtb_profile_begin.argtypes = [ctypes.c_char_p]
     L.mtb_profile_begin.restype = ctypes.c_int
     L.mtb_profile_end.argtypes = [ctypes.POINTER(_KernelTime), i32, ctypes.POINTER(i32)]
@@ -236,7 +250,7 @@ def mtb_bitmaps(pyramid: torch.Tensor, width: int, height: int, levels: int, exc
 
 def mtb_align_pair(bm_ref: torch.Tensor, bm_mov: torch.Tensor, width: int, height: int,
                    levels: int, workspace: torch.Tensor | None = None, trace: bool = False,
-                   level_shifts: bool = False, stream=None) -> dict:
+                   level_shifts: bool = False, shift=None, err=None, stream=None) -> dict:
     """Coarse-to-fine search of the moving bitmaps against the reference's.
 
     Returns device tensors ``shift`` int32[2] (dx, dy), ``err`` int32[1] (the uint32
@@ -247,8 +261,10 @@ def mtb_align_pair(bm_ref: torch.Tensor, bm_mov: torch.Tensor, width: int, heigh
     _device_u8(bm_mov, "bm_mov")
     dev = bm_ref.device
     workspace = _buffer(max(mtb_pair_workspace_bytes(levels), 1), dev, workspace)
-    shift = torch.empty(2, dtype=torch.int32, device=dev)
-    err = torch.empty(1, dtype=torch.int32, device=dev)
+    if shift is None:
+        shift = torch.empty(2, dtype=torch.int32, device=dev)
+    if err is None:
+        err = torch.empty(1, dtype=torch.int32, device=dev)
     tr = torch.empty((levels, 9), dtype=torch.int32, device=dev) if trace else None
     ls = torch.empty((levels, 2), dtype=torch.int32, device=dev) if level_shifts else None
     _check("mtb_align_pair",
@@ -287,6 +303,48 @@ def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int 
                                  _ptr(workspace), workspace.numel(), _ptr(shifts), _ptr(errs),
                                  _ptr(tr), _stream(stream)))
     return {"shifts": shifts, "errs": errs, "trace": tr, "workspace": workspace}
+
+
+def _batch_items(pairs):
+    """[(ref, mov, levels), ...] of (H, W, 3) device images -> ctypes item array."""
+    n = len(pairs)
+    if not 1 <= n <= MTB_MAX_BATCH:
+        raise ValueError(f"a batch holds 1..{MTB_MAX_BATCH} items")
+    items = (_BatchItem * n)()
+    for i, (ref, mov, levels) in enumerate(pairs):
+        geo = _rgb_geometry(ref)
+        if _rgb_geometry(mov) != geo or mov.device != ref.device:
+            raise ValueError("the two images of an item must share size, stride and device")
+        W, H, stride = geo
+        items[i] = _BatchItem(ref.data_ptr(), mov.data_ptr(), stride, W, H, int(levels), 0)
+    return items
+
+
+def mtb_batch_workspace_bytes(pairs) -> int:
+    """Workspace bytes for mtb_align_batch over [(ref, mov, levels), ...]."""
+    items = _batch_items(pairs)
+    return int(lib().mtb_batch_workspace_bytes(items, len(pairs)))
+
+
+def mtb_align_batch(pairs, exclude_range: int = 4, workspace: torch.Tensor | None = None,
+                    shifts=None, errs=None, stream=None) -> dict:
+    """Align every (ref, mov, levels) item of a batch; sizes may differ between items.
+
+    Returns device tensors ``shifts`` int32[n][2] and ``errs`` int32[n].
+    """
+    items = _batch_items(pairs)
+    n = len(pairs)
+    dev = pairs[0][0].device
+    need = int(lib().mtb_batch_workspace_bytes(items, n))
+    workspace = _buffer(max(need, 1), dev, workspace)
+    if shifts is None:
+        shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    if errs is None:
+        errs = torch.empty(n, dtype=torch.int32, device=dev)
+    _check("mtb_align_batch",
+           lib().mtb_align_batch(items, n, exclude_range, _ptr(workspace), workspace.numel(),
+                                 _ptr(shifts), _ptr(errs), _stream(stream)))
+    return {"shifts": shifts, "errs": errs, "workspace": workspace}
 
 
 def mtb_profile_begin(kernel_name: str | None = None) -> None:

@@ -4,6 +4,7 @@
 
 #include <mutex>
 #include <string.h>
+#include <vector>
 
 #include "mtb_internal.h"
 
@@ -112,6 +113,132 @@ void fill_chunk_starts(const Geometry &g, int64_t *cs)
     }
 }
 
+// One launch set: n images of one size, each image's pyramid and bitmaps
+// built once, then the search of npairs pairs of them (reference ref_img[p]
+// against moving image mov_img[p], results in output row out_row[p]).
+struct PairSet {
+    const uint8_t *rgb[kMaxStack];
+    int n = 0;
+    int ref_img[kMaxStack], mov_img[kMaxStack], out_row[kMaxStack];
+    int npairs = 0;
+};
+
+// Workspace bytes of a launch set (from a 256-byte aligned start): pyramids,
+// bitmaps, each pair's search state, ticket counters.
+int64_t set_workspace_bytes(const Geometry &g, int n, int npairs)
+{
+    return n * (g.pyramid_bytes + g.bitmaps_bytes) + npairs * state_stride_words(g.L) * 4 +
+           align_up(4 * kTicketWords, kAlign);
+}
+
+// Enqueues a launch set on s.  `ws` is 256-byte aligned; `zero` lists output
+// regions to clear first (taken by value, its free slots are used here).
+hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int align, int exclude,
+                       uint8_t *ws, SearchOutputs out, ZeroArgs zero, int cus, hipStream_t s)
+{
+    const int n = ps.n, npairs = ps.npairs;
+    uint8_t *pyr0 = ws;
+    uint8_t *bm0 = pyr0 + n * g.pyramid_bytes;
+    uint32_t *state = (uint32_t *)(bm0 + n * g.bitmaps_bytes);
+    const int64_t sstride = state_stride_words(g.L);
+
+    for (int i = 0; i < n; ++i) {
+        zero.ptr[zero.count] = (uint32_t *)(pyr0 + i * g.pyramid_bytes + g.hist_off);
+        zero.words[zero.count++] = (int64_t)g.L * 256;
+    }
+    zero.ptr[zero.count] = state;
+    zero.words[zero.count++] = sstride * npairs + kTicketWords;  // every pair's search state, then the tickets
+    hipError_t e = launch_zero(zero, s);
+    if (e != hipSuccess)
+        return e;
+
+    PyramidArgs pa;
+    memset(&pa, 0, sizeof(pa));
+    for (int i = 0; i < n; ++i) {
+        pa.rgb[i] = ps.rgb[i];
+        pa.pyr[i] = pyr0 + i * g.pyramid_bytes;
+    }
+    pa.stride = stride;
+    pa.n = n;
+    pa.align = align;
+    pa.g = g;
+    e = launch_pyramid(pa, cus, s);
+    if (e != hipSuccess)
+        return e;
+
+    BitmapArgs ba;
+    memset(&ba, 0, sizeof(ba));
+    for (int i = 0; i < n; ++i) {
+        ba.pyr[i] = pyr0 + i * g.pyramid_bytes;
+        ba.bm[i] = bm0 + i * g.bitmaps_bytes;
+    }
+    ba.n = n;
+    ba.exclude = exclude;
+    ba.g = g;
+    fill_chunk_starts(g, ba.chunk_start);
+    e = launch_bitmaps(ba, cus, s);
+    if (e != hipSuccess || npairs == 0)
+        return e;
+
+    SearchArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    for (int p = 0; p < npairs; ++p) {
+        sa.ref[p] = bm0 + ps.ref_img[p] * g.bitmaps_bytes;
+        sa.mov[p] = bm0 + ps.mov_img[p] * g.bitmaps_bytes;
+        out.pair_image[p] = ps.out_row[p];
+    }
+    sa.state = state;
+    sa.done = state + sstride * npairs;
+    sa.state_stride = sstride;
+    sa.npairs = npairs;
+    sa.out = out;
+    sa.g = g;
+    return launch_search(sa, cus, s);
+}
+
+// Items of a batch that share one launch set: same geometry and stride, at
+// most kMaxStack / 2 pairs.
+struct BatchGroup {
+    int first;  // an item of the group, for its geometry and stride
+    std::vector<int> items;
+};
+
+// Splits a valid item list into launch sets, in order of first appearance.
+std::vector<BatchGroup> batch_groups(const mtb_batch_item *it, int n)
+{
+    std::vector<BatchGroup> groups;
+    std::vector<int> open;  // index into groups of the last group of each size seen
+    for (int i = 0; i < n; ++i) {
+        int found = -1;
+        for (int k : open) {
+            const mtb_batch_item &f = it[groups[k].first];
+            if (f.width == it[i].width && f.height == it[i].height && f.levels == it[i].levels &&
+                f.row_stride == it[i].row_stride) {
+                found = k;
+                break;
+            }
+        }
+        if (found >= 0 && (int)groups[found].items.size() == kMaxStack / 2) {
+            for (int &k : open)
+                if (k == found)
+                    k = (int)groups.size();
+            groups.push_back(BatchGroup{i, {i}});
+        } else if (found >= 0) {
+            groups[found].items.push_back(i);
+        } else {
+            open.push_back((int)groups.size());
+            groups.push_back(BatchGroup{i, {i}});
+        }
+    }
+    return groups;
+}
+
+bool batch_item_valid(const mtb_batch_item &it, Geometry *g)
+{
+    return it.d_ref_rgb && it.d_mov_rgb && it.reserved == 0 && make_geometry(it.width, it.height, it.levels, g) &&
+           it.row_stride >= 3 * (int64_t)it.width;
+}
+
 }  // namespace
 }  // namespace mtb
 
@@ -192,8 +319,7 @@ size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32
     if (n < 1 || n > kMaxStack || !make_geometry(width, height, levels, &g))
         return 0;
     // pyramids, bitmaps, search state, ticket counters, plus slack to align the start
-    return (size_t)(n * (g.pyramid_bytes + g.bitmaps_bytes) + (n - 1) * state_stride_words(levels) * 4 +
-                    align_up(4 * kTicketWords, kAlign) + kAlign);
+    return (size_t)(set_workspace_bytes(g, n, n - 1) + kAlign);
 }
 
 mtb_status mtb_build_pyramid(const uint8_t *d_rgb, int32_t width, int32_t height,
@@ -329,25 +455,25 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
         return MTB_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
 
-    // Workspace: pyramids, bitmaps, then search state, from a 256-byte aligned start.
-    uint8_t *base = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
-    uint8_t *pyr0 = base;
-    uint8_t *bm0 = pyr0 + n * g.pyramid_bytes;
-    uint32_t *state = (uint32_t *)(bm0 + n * g.bitmaps_bytes);
-    const int64_t sstride = state_stride_words(levels);
-    const int npairs = n - 1;
-    uint32_t *done = state + sstride * npairs;
-
+    PairSet ps;
+    for (int i = 0; i < n; ++i) {
+        ps.rgb[i] = h_d_rgb[i];
+        if (i != ref) {
+            ps.ref_img[ps.npairs] = ref;
+            ps.mov_img[ps.npairs] = i;
+            ps.out_row[ps.npairs++] = i;
+        }
+    }
+    ps.n = n;
+    SearchOutputs out;
+    memset(&out, 0, sizeof(out));
+    out.n_out = n;
+    out.shifts = d_shifts;
+    out.errs = d_errs;
+    out.trace = d_trace;
+    // The reference's output rows stay zero; the search writes every other row.
     ZeroArgs z;
     memset(&z, 0, sizeof(z));
-    for (int i = 0; i < n; ++i) {
-        z.ptr[i] = (uint32_t *)(pyr0 + i * g.pyramid_bytes + g.hist_off);
-        z.words[i] = (int64_t)levels * 256;
-    }
-    z.ptr[n] = state;
-    z.words[n] = sstride * npairs + kTicketWords;  // every pair's search state, then the tickets
-    z.count = n + 1;
-    // The reference's output rows stay zero; the search writes every other row.
     z.ptr[z.count] = (uint32_t *)d_shifts;
     z.words[z.count++] = 2 * (int64_t)n;
     z.ptr[z.count] = d_errs;
@@ -356,59 +482,76 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
         z.ptr[z.count] = d_trace;
         z.words[z.count++] = 9 * (int64_t)levels * n;
     }
-    if (launch_zero(z, s) != hipSuccess)
-        return MTB_ERR_DEVICE;
+    uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
+    return device_status(enqueue_set(ps, g, row_stride, align, exclude_range, ws, out, z, cus, s));
+}
 
-    PyramidArgs pa;
-    memset(&pa, 0, sizeof(pa));
-    for (int i = 0; i < n; ++i) {
-        pa.rgb[i] = h_d_rgb[i];
-        pa.pyr[i] = pyr0 + i * g.pyramid_bytes;
+size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items)
+{
+    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH)
+        return 0;
+    Geometry g;
+    for (int i = 0; i < n_items; ++i)
+        if (!batch_item_valid(h_items[i], &g))
+            return 0;
+    int64_t most = 0;
+    for (const BatchGroup &grp : batch_groups(h_items, n_items)) {
+        const mtb_batch_item &f = h_items[grp.first];
+        make_geometry(f.width, f.height, f.levels, &g);
+        const int np = (int)grp.items.size();
+        const int64_t b = set_workspace_bytes(g, 2 * np, np);
+        most = b > most ? b : most;
     }
-    pa.stride = row_stride;
-    pa.n = n;
-    pa.align = align;
-    pa.g = g;
-    if (launch_pyramid(pa, cus, s) != hipSuccess)
-        return MTB_ERR_DEVICE;
+    return (size_t)(most + kAlign);
+}
 
-    BitmapArgs ba;
-    memset(&ba, 0, sizeof(ba));
-    for (int i = 0; i < n; ++i) {
-        ba.pyr[i] = pyr0 + i * g.pyramid_bytes;
-        ba.bm[i] = bm0 + i * g.bitmaps_bytes;
+mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range,
+                           void *d_workspace, size_t workspace_bytes, int32_t *d_shifts,
+                           uint32_t *d_errs, void *stream)
+{
+    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH || !d_workspace || !d_shifts || !d_errs)
+        return MTB_ERR_INVALID_ARG;
+    if (exclude_range < 0 || exclude_range > 255)
+        return MTB_ERR_INVALID_ARG;
+    Geometry g;
+    for (int i = 0; i < n_items; ++i)
+        if (!batch_item_valid(h_items[i], &g))
+            return MTB_ERR_INVALID_ARG;
+    if (workspace_bytes < mtb_batch_workspace_bytes(h_items, n_items))
+        return MTB_ERR_WORKSPACE;
+    const int cus = current_device_cus();
+    if (cus <= 0)
+        return MTB_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
+    for (const BatchGroup &grp : batch_groups(h_items, n_items)) {
+        const mtb_batch_item &f = h_items[grp.first];
+        make_geometry(f.width, f.height, f.levels, &g);
+        PairSet ps;
+        int align = 16;
+        for (int k : grp.items) {
+            const mtb_batch_item &it = h_items[k];
+            ps.ref_img[ps.npairs] = ps.n;
+            ps.rgb[ps.n++] = it.d_ref_rgb;
+            ps.mov_img[ps.npairs] = ps.n;
+            ps.rgb[ps.n++] = it.d_mov_rgb;
+            ps.out_row[ps.npairs++] = k;
+            const int a1 = row_alignment(it.d_ref_rgb, it.row_stride), a2 = row_alignment(it.d_mov_rgb, it.row_stride);
+            align = a1 < align ? a1 : align;
+            align = a2 < align ? a2 : align;
+        }
+        SearchOutputs out;
+        memset(&out, 0, sizeof(out));
+        out.n_out = n_items;
+        out.shifts = d_shifts;
+        out.errs = d_errs;
+        ZeroArgs z;
+        memset(&z, 0, sizeof(z));
+        const hipError_t e = enqueue_set(ps, g, f.row_stride, align, exclude_range, ws, out, z, cus, s);
+        if (e != hipSuccess)
+            return MTB_ERR_DEVICE;
     }
-    ba.n = n;
-    ba.exclude = exclude_range;
-    ba.g = g;
-    fill_chunk_starts(g, ba.chunk_start);
-    if (launch_bitmaps(ba, cus, s) != hipSuccess)
-        return MTB_ERR_DEVICE;
-    if (npairs == 0)
-        return MTB_OK;
-
-    SearchArgs sa;
-    memset(&sa, 0, sizeof(sa));
-    int p = 0;
-    for (int i = 0; i < n; ++i) {
-        if (i == ref)
-            continue;
-        sa.ref[p] = bm0 + ref * g.bitmaps_bytes;
-        sa.mov[p] = bm0 + i * g.bitmaps_bytes;
-        sa.out.pair_image[p] = i;
-        ++p;
-    }
-    sa.state = state;
-    sa.done = done;
-    sa.state_stride = sstride;
-    sa.npairs = npairs;
-    sa.out.n_out = n;
-    sa.out.shifts = d_shifts;
-    sa.out.errs = d_errs;
-    sa.out.trace = d_trace;
-    sa.out.level_shifts = nullptr;
-    sa.g = g;
-    return device_status(launch_search(sa, cus, s));
+    return MTB_OK;
 }
 
 }  // extern "C"

@@ -161,9 +161,28 @@ def expose(rad: np.ndarray, ev: float, gain: float = 1.0) -> np.ndarray:
 def translate(img: np.ndarray, tx: int, ty: int) -> np.ndarray:
     """Edge-replicate translation: out[y][x] = img[clamp(y - ty)][clamp(x - tx)]."""
     H, W = img.shape[:2]
-    iy = np.clip(np.arange(H) - int(ty), 0, H - 1)
-    ix = np.clip(np.arange(W) - int(tx), 0, W - 1)
-    return np.ascontiguousarray(img[iy][:, ix])
+    tx, ty = int(tx), int(ty)
+
+    def shift_cols(dst, src):
+        # dst[:, x] = src[:, clamp(x - tx)]
+        xs, xe = min(max(tx, 0), W), max(min(W + tx, W), 0)
+        if xs < xe:
+            dst[:, xs:xe] = src[:, xs - tx:xe - tx]
+            dst[:, :xs] = src[:, :1]
+            dst[:, xe:] = src[:, W - 1:W]
+        else:
+            dst[:] = src[:, :1] if tx > 0 else src[:, W - 1:W]
+
+    out = np.empty_like(img)
+    ys, ye = min(max(ty, 0), H), max(min(H + ty, H), 0)
+    if ys < ye:
+        shift_cols(out[ys:ye], img[ys - ty:ye - ty])
+        out[:ys] = out[ys]
+        out[ye:] = out[ye - 1]
+    else:
+        shift_cols(out[:1], img[:1] if ty > 0 else img[H - 1:H])
+        out[1:] = out[0]
+    return out
 
 
 def saturation_gain(rad: np.ndarray, evs, frac: float) -> float:
@@ -252,6 +271,37 @@ class Workload:
     @property
     def megapixels(self) -> float:
         return sum(len(s[0]) for s in self.stacks) * self.width * self.height / 1e6
+
+
+# Sizes (width, height, levels, blobs) of the uneven-batch workload.
+BATCH_SIZES = ((640, 480, 5, 40), (1920, 1080, 6, 400), (4000, 3000, 7, 400), (6000, 4000, 7, 400))
+
+
+def make_batch(n_pairs, seed, sizes=BATCH_SIZES, evs=(0.0, -2.0)):
+    """A batch of 2-stop exposure pairs of uneven sizes.
+
+    Each pair's size is drawn uniformly from ``sizes``; each size class has one
+    radiance field (drawn in the order of ``sizes``) whose two exposures every
+    pair of the class shares, the moving one translated by the pair's own
+    shift t in [-2^(L-1), 2^(L-1)]^2 (edge replicate), drawn in pair order
+    after the sizes.  Returns [(ref, mov, (tx, ty), levels), ...].
+    """
+    rng = np.random.default_rng(seed)
+    cls = [int(c) for c in rng.integers(0, len(sizes), n_pairs)]
+    shifts = []
+    for c in cls:
+        r = 1 << (sizes[c][2] - 1)
+        shifts.append(tuple(int(v) for v in rng.integers(-r, r + 1, 2)))
+    exposures = {}
+    for c in sorted(set(cls)):
+        W, H, _, blobs = sizes[c]
+        rad = radiance_field(W, H, blobs, rng)
+        exposures[c] = (expose(rad, evs[0]), expose(rad, evs[1]))
+    out = []
+    for c, (tx, ty) in zip(cls, shifts):
+        ref, mov = exposures[c]
+        out.append((ref, translate(mov, tx, ty), (tx, ty), sizes[c][2]))
+    return out
 
 
 def workload(name: str) -> Workload:

@@ -186,3 +186,51 @@ def test_valid_call_without_gpu_is_unsupported(mtb):
     L = _c(mtb)
     need = mtb.mtb_pyramid_bytes(64, 48, 3)
     assert L.mtb_build_pyramid(FAKE, 64, 48, 192, 3, FAKE, need, NULL) == 4
+
+
+def _items(mtb, specs):
+    from paper_2007_06483_amd import _BatchItem
+
+    arr = (_BatchItem * len(specs))()
+    for i, (w, h, L, stride) in enumerate(specs):
+        arr[i] = _BatchItem(0x1000 + 0x100 * i, 0x9000 + 0x100 * i, stride, w, h, L, 0)
+    return arr
+
+
+def test_batch_workspace_is_the_largest_group(mtb):
+    L = _c(mtb)
+    specs = [(64, 48, 3, 192), (32, 24, 2, 96), (64, 48, 3, 192), (64, 48, 3, 256)]
+    items = _items(mtb, specs)
+    got = L.mtb_batch_workspace_bytes(items, len(specs))
+    # Groups: (64x48, stride 192) x2, (32x24) x1, (64x48, stride 256) x1; each
+    # group's need is at most that of its images as a stack, plus search state.
+    two = mtb.mtb_stack_workspace_bytes(4, 64, 48, 3)
+    assert mtb.mtb_stack_workspace_bytes(2, 64, 48, 3) < got <= two + 4096
+    # 17 equal items split into 16 + 1: the workspace is that of the 16.
+    items17 = _items(mtb, [(64, 48, 3, 192)] * 17)
+    items16 = _items(mtb, [(64, 48, 3, 192)] * 16)
+    assert L.mtb_batch_workspace_bytes(items17, 17) == L.mtb_batch_workspace_bytes(items16, 16)
+    assert L.mtb_batch_workspace_bytes(items16, 16) > L.mtb_batch_workspace_bytes(items16, 8)
+
+
+def test_batch_validation(mtb):
+    L = _c(mtb)
+    items = _items(mtb, [(64, 48, 3, 192), (32, 24, 2, 96)])
+    ws = L.mtb_batch_workspace_bytes(items, 2)
+    assert ws > 0
+    assert L.mtb_batch_workspace_bytes(NULL, 2) == 0
+    assert L.mtb_batch_workspace_bytes(items, 0) == 0
+    args = [items, 2, 4, FAKE, ws, FAKE, FAKE, NULL]
+    for i, v in ((0, NULL), (1, 0), (1, 4097), (2, -1), (2, 256), (3, NULL), (5, NULL), (6, NULL)):
+        bad = list(args)
+        bad[i] = v
+        assert L.mtb_align_batch(*bad) == 1, (i, v)
+    bad = list(args)
+    bad[4] = ws - 1
+    assert L.mtb_align_batch(*bad) == 2
+    for field, value in (("levels", 7), ("levels", 0), ("row_stride", 95), ("reserved", 1),
+                         ("d_ref_rgb", None), ("width", 0)):
+        broken = _items(mtb, [(64, 48, 3, 192), (32, 24, 2, 96)])
+        setattr(broken[1], field, value)
+        assert L.mtb_batch_workspace_bytes(broken, 2) == 0, field
+        assert L.mtb_align_batch(broken, 2, 4, FAKE, ws, FAKE, FAKE, NULL) == 1, field
