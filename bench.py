@@ -218,13 +218,88 @@ def run_batch(args, mtb, synth, torch, np, dev):
     print(json.dumps(result), flush=True)
 
 
+def run_served(args, mtb, synth, torch, np, dev):
+    """Poisson arrivals of exposure stacks served with continuous batching (device-staged:
+    the requests are crops of a base scene resident on the GPU)."""
+    from paper_2007_06483_amd.serving import Request, Server, gpu_executor, percentile
+
+    BW, BH = 8704, 5888
+    log(f"generating the {BW}x{BH} 9-exposure base scene ...")
+    t0 = time.perf_counter()
+    base = synth.make_serve_base(BW, BH, 5)
+    base_dev = [torch.from_numpy(b).to(dev) for b in base]
+    del base
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+
+    def requests(seed, rate, seconds):
+        specs = synth.serve_requests(seed, rate, seconds, BW, BH)
+        out = []
+        for r in specs:
+            imgs = [synth.serve_crop(base_dev, r, i) for i in range(r["n"])]
+            out.append(Request(rid=r["rid"], arrival=r["arrival"], images=imgs, levels=r["levels"],
+                               workspace_bytes=mtb.mtb_stack_workspace_bytes(r["n"], r["width"], r["height"],
+                                                                             r["levels"]),
+                               megapixels=r["n"] * r["width"] * r["height"] / 1e6))
+        return out
+
+    slots = args.serve_slots
+    pool_bytes = 24 << 30
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device=dev)
+    execute, poll = gpu_executor(pool, slots)
+
+    def serve(rate, seconds, seed):
+        reqs = requests(seed, rate, seconds)
+        srv = Server(pool_bytes, slots, execute, poll)
+        res = srv.run(reqs)
+        torch.cuda.synchronize()
+        lat = [r.latency * 1e3 for r in res]
+        span = max(r.completed for r in res) - min(r.arrival for r in res)
+        mp = sum(q.megapixels for q in reqs)
+        return {"offered_per_s": rate, "requests": len(reqs), "p50_ms": round(percentile(lat, 50), 3),
+                "p99_ms": round(percentile(lat, 99), 3), "MPps": round(mp / span, 1),
+                "offered_MPps": round(mp / seconds, 1), "max_in_flight": srv.max_in_flight}
+
+    serve(200.0, 0.5, 99)  # warm-up
+    log(f"serving Poisson(200/s) for {args.serve_seconds:.0f} s ...")
+    main_run = serve(200.0, args.serve_seconds, 5)
+    log(json.dumps(main_run))
+    sweep = []
+    for rate in (800.0, 1600.0, 3200.0, 6400.0):
+        sweep.append(serve(rate, 3.0, 50 + int(rate)))
+        log(json.dumps(sweep[-1]))
+    result = {
+        "metric": METRIC,
+        "value": main_run["MPps"],
+        "unit": "MP/s",
+        "n_gpus": 1,
+        "steps": main_run["requests"],
+        "warmup": 1,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "served_poisson200", "rate_per_s": 200, "seconds": args.serve_seconds,
+                   "slots": slots, "pool_GiB": pool_bytes >> 30, "staging": "device (crops of a resident base)",
+                   "base": f"{BW}x{BH}x9"},
+        "latency_ms": {"p50": main_run["p50_ms"], "p99": main_run["p99_ms"]},
+        "served": main_run,
+        "saturation_sweep": sweep,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stack7_6000x4000",
-                    choices=["stack7_6000x4000", "pair_4096x3072", "pair_512x384", "batch64_uneven"])
+                    choices=["stack7_6000x4000", "pair_4096x3072", "pair_512x384", "batch64_uneven",
+                             "served_poisson200"])
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
+    ap.add_argument("--serve-slots", type=int, default=4, help="served mode: stacks in flight at most")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -254,6 +329,8 @@ def main():
 
     if args.workload == "batch64_uneven":
         return run_batch(args, mtb, synth, torch, np, dev)
+    if args.workload == "served_poisson200":
+        return run_served(args, mtb, synth, torch, np, dev)
 
     log(f"generating {args.workload} ...")
     t0 = time.perf_counter()

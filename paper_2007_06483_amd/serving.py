@@ -1,0 +1,222 @@
+"""Served alignment: a request loop with continuous batching on one GPU.
+
+Exposure stacks arrive over time.  A request is admitted as soon as an
+execution slot (a HIP stream) is free and its workspace fits in the device
+memory set aside for serving (admission by HBM footprint); requests that
+arrive while others run are admitted as slots and memory free up, and the
+stacks in flight overlap on the device.  Each admitted stack is one
+``mtb_align_stack`` call on its slot's stream with a workspace carved out of
+the serving pool; its pyramids and bitmaps stay on the device.  Latency is
+completion minus arrival.
+
+The loop is host logic only: every step of the alignment runs in libmtb's
+kernels.  The executor is a parameter so that the admission and retirement
+logic can be exercised without a GPU.
+"""
+
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable
+
+
+@dataclasses.dataclass
+class Request:
+    """One alignment request: a stack of same-size images (device tensors)."""
+
+    rid: int
+    arrival: float          # seconds after the start of the run
+    images: list
+    levels: int
+    ref_index: int = -1
+    exclude_range: int = 4
+    workspace_bytes: int = 0
+    megapixels: float = 0.0
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    completed: float
+    shifts: object = None
+    errs: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.arrival
+
+
+class FootprintPool:
+    """First-fit allocator of byte ranges in a fixed region (alignment 256).
+
+    Host-side bookkeeping only: it hands out offsets into one device buffer.
+    """
+
+    ALIGN = 256
+
+    def __init__(self, capacity: int):
+        if capacity <= 0:
+            raise ValueError("capacity must be positive")
+        self.capacity = int(capacity)
+        self._free = [(0, self.capacity)]  # sorted, disjoint (offset, size)
+        self._used = {}
+
+    def alloc(self, nbytes: int):
+        """Offset of a free range of at least nbytes, or None if none fits."""
+        size = -(-int(nbytes) // self.ALIGN) * self.ALIGN
+        if size <= 0:
+            size = self.ALIGN
+        for i, (off, avail) in enumerate(self._free):
+            if avail >= size:
+                if avail == size:
+                    del self._free[i]
+                else:
+                    self._free[i] = (off + size, avail - size)
+                self._used[off] = size
+                return off
+        return None
+
+    def free(self, off: int) -> None:
+        size = self._used.pop(off)
+        self._free.append((off, size))
+        self._free.sort()
+        merged = []
+        for o, s in self._free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + s)
+            else:
+                merged.append((o, s))
+        self._free = merged
+
+    @property
+    def in_use(self) -> int:
+        return sum(self._used.values())
+
+
+class Server:
+    """Continuous-batching request loop.
+
+    executor(req, slot, offset) enqueues request ``req`` on slot ``slot`` with
+    workspace at byte ``offset`` of the pool and returns a handle;
+    poll(handle) returns None while it runs and (shifts, errs) once done.
+    """
+
+    def __init__(self, pool_bytes: int, slots: int, executor: Callable, poll: Callable,
+                 clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
+                 idle_sleep: float = 50e-6):
+        if slots < 1:
+            raise ValueError("at least one slot")
+        self.pool = FootprintPool(pool_bytes)
+        self.slots = slots
+        self.executor = executor
+        self.poll = poll
+        self.clock = clock
+        self.sleep = sleep
+        self.idle_sleep = idle_sleep
+        self.max_in_flight = 0
+
+    def run(self, requests) -> list:
+        """Serve requests (any order; each has an arrival time) in real time."""
+        for r in requests:
+            if r.workspace_bytes > self.pool.capacity:
+                raise ValueError(f"request {r.rid} needs {r.workspace_bytes} bytes, "
+                                 f"more than the pool's {self.pool.capacity}")
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting = collections.deque()
+        free_slots = list(range(self.slots - 1, -1, -1))
+        in_flight = []  # (req, slot, offset, handle, admitted)
+        results = []
+        t0 = self.clock()
+        while pending or waiting or in_flight:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            progressed = False
+            still = []
+            for item in in_flight:
+                req, slot, off, handle, admitted = item
+                out = self.poll(handle)
+                if out is None:
+                    still.append(item)
+                    continue
+                done = self.clock() - t0
+                self.pool.free(off)
+                free_slots.append(slot)
+                results.append(Result(req.rid, req.arrival, admitted, done, out[0], out[1]))
+                progressed = True
+            in_flight = still
+            # Admission in arrival order: a request that does not fit waits for
+            # memory to free up (no overtaking, so no starvation).
+            while waiting and free_slots:
+                req = waiting[0]
+                off = self.pool.alloc(req.workspace_bytes)
+                if off is None:
+                    break
+                waiting.popleft()
+                slot = free_slots.pop()
+                admitted = self.clock() - t0
+                handle = self.executor(req, slot, off)
+                in_flight.append((req, slot, off, handle, admitted))
+                progressed = True
+            self.max_in_flight = max(self.max_in_flight, len(in_flight))
+            if not progressed:
+                if not in_flight and not waiting and pending:
+                    wait = pending[0].arrival - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(min(wait, 0.01))
+                else:
+                    self.sleep(self.idle_sleep)
+        results.sort(key=lambda r: r.rid)
+        return results
+
+
+def percentile(values, q: float) -> float:
+    """q-th percentile (0..100) by linear interpolation between order statistics."""
+    v = sorted(values)
+    if not v:
+        return float("nan")
+    pos = (len(v) - 1) * q / 100.0
+    lo = int(pos)
+    hi = min(lo + 1, len(v) - 1)
+    return v[lo] + (v[hi] - v[lo]) * (pos - lo)
+
+
+def gpu_executor(pool_buffer, slots: int):
+    """Executor and poll functions that run requests through libmtb on `slots` streams.
+
+    pool_buffer is a uint8 device tensor holding the serving pool; request
+    workspaces are views into it.  Streams are created at default priority.
+    """
+    import torch
+
+    import paper_2007_06483_amd as mtb
+
+    streams = [torch.cuda.Stream(device=pool_buffer.device) for _ in range(slots)]
+
+    def execute(req, slot, off):
+        s = streams[slot]
+        # Inputs were produced on the current stream; the slot's stream waits for them.
+        s.wait_stream(torch.cuda.current_stream(pool_buffer.device))
+        ws = pool_buffer[off:off + req.workspace_bytes]
+        n = len(req.images)
+        with torch.cuda.stream(s):
+            shifts = torch.empty((n, 2), dtype=torch.int32, device=pool_buffer.device)
+            errs = torch.empty(n, dtype=torch.int32, device=pool_buffer.device)
+            mtb.mtb_align_stack(req.images, req.levels, exclude_range=req.exclude_range,
+                                ref_index=req.ref_index, workspace=ws, shifts=shifts, errs=errs,
+                                stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return (ev, shifts, errs)
+
+    def poll(handle):
+        ev, shifts, errs = handle
+        if not ev.query():
+            return None
+        return shifts, errs
+
+    return execute, poll

@@ -304,6 +304,76 @@ def make_batch(n_pairs, seed, sizes=BATCH_SIZES, evs=(0.0, -2.0)):
     return out
 
 
+def serve_levels(width: int, height: int) -> int:
+    """Levels of a served request: min(7, 1 + floor(log2(min(W, H) / 32)))."""
+    m = min(int(width), int(height))
+    L = 1
+    while L < 7 and (32 << L) <= m:
+        L += 1
+    return L
+
+
+def make_serve_base(width, height, seed, n_exposures=9, n_blobs=400):
+    """Base scene of the served workload: one radiance field, exposures 2^(e - n//2).
+
+    Returns the list of (H, W, 3) uint8 exposures (index n//2 is 2^0).
+    """
+    rng = np.random.default_rng(seed)
+    rad = radiance_field(width, height, n_blobs, rng)
+    return [expose(rad, float(e - n_exposures // 2)) for e in range(n_exposures)]
+
+
+def serve_requests(seed, rate, duration, base_width, base_height, n_exposures=9,
+                   mp_range=(1.0, 48.0), n_range=(3, 9), aspect=1.5):
+    """Poisson arrivals of exposure-stack requests cut from a base scene.
+
+    Arrivals: exponential gaps with mean 1/rate until ``duration`` seconds.  Per
+    request, in this order: n ~ U{n_range}; megapixels log-uniform over
+    mp_range at the given aspect (W = round(sqrt(MP 1e6 aspect)), H =
+    round(W / aspect), shrunk if needed to fit the base with margins); levels
+    L = serve_levels(W, H), R = 2^(L-1); the reference crop's corner (x0, y0)
+    uniform with every crop inside the base; offsets (dx, dy) in [-R, R]^2 for
+    each non-reference image (the reference, index n//2, is at offset 0).
+    Image i is exposure (n_exposures//2 + i - n//2) of the base cropped at
+    (x0 + dx_i, y0 + dy_i); the shift that aligns it is (dx_i, dy_i).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration:
+            break
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        lo, hi = math.log(mp_range[0]), math.log(mp_range[1])
+        mp = math.exp(float(rng.uniform(lo, hi)))
+        W = int(round(math.sqrt(mp * 1e6 * aspect)))
+        H = int(round(W / aspect))
+        L = serve_levels(W, H)
+        R = 1 << (L - 1)
+        W = min(W, base_width - 2 * R)
+        H = min(H, base_height - 2 * R)
+        L = serve_levels(W, H)
+        R = 1 << (L - 1)
+        x0 = int(rng.integers(R, base_width - W - R + 1))
+        y0 = int(rng.integers(R, base_height - H - R + 1))
+        offsets = []
+        for i in range(n):
+            d = tuple(int(v) for v in rng.integers(-R, R + 1, 2))
+            offsets.append((0, 0) if i == n // 2 else d)
+        exposures = [n_exposures // 2 + i - n // 2 for i in range(n)]
+        out.append(dict(rid=len(out), arrival=t, n=n, width=W, height=H, levels=L, x0=x0, y0=y0,
+                        offsets=offsets, exposures=exposures))
+    return out
+
+
+def serve_crop(base, req, i):
+    """Image i of a served request as a view of the base exposures (any array type)."""
+    dx, dy = req["offsets"][i]
+    x, y = req["x0"] + dx, req["y0"] + dy
+    return base[req["exposures"][i]][y:y + req["height"], x:x + req["width"]]
+
+
 def workload(name: str) -> Workload:
     """The named synthetic workloads (sizes, seeds and ranges fixed here).
 

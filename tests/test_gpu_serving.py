@@ -1,0 +1,69 @@
+"""Served alignment on the GPU: each stack's result in the mix equals its result alone.
+
+Requests are cut from a small base scene and arrive as a Poisson stream with
+an initial burst, so several stacks are in flight at once on different
+streams with workspaces from one pool.  Every served result must equal the
+result of aligning that stack alone (bit-exact), and a sample must equal the
+oracle.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def mtb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_06483_amd as m
+
+    m.lib()
+    return m
+
+
+@pytest.mark.timeout(600)
+def test_served_results_equal_results_alone(mtb):
+    from paper_2007_06483_amd.serving import Request, Server, gpu_executor
+
+    BW, BH = 1536, 1024
+    base = synth.make_serve_base(BW, BH, 6, n_blobs=60)
+    base_dev = [torch.from_numpy(b).to(DEV) for b in base]
+    specs = synth.serve_requests(7, 400.0, 0.15, BW, BH, mp_range=(0.05, 0.6))
+    assert len(specs) >= 20
+    reqs = []
+    for k, r in enumerate(specs):
+        imgs = [synth.serve_crop(base_dev, r, i) for i in range(r["n"])]
+        ws = mtb.mtb_stack_workspace_bytes(r["n"], r["width"], r["height"], r["levels"])
+        # The first eight arrive together: a burst that fills every slot.
+        reqs.append(Request(rid=r["rid"], arrival=0.0 if k < 8 else r["arrival"], images=imgs,
+                            levels=r["levels"], workspace_bytes=ws))
+    slots = 4
+    pool_bytes = slots * max(q.workspace_bytes for q in reqs) + 4096
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device=DEV)
+    execute, poll = gpu_executor(pool, slots)
+    srv = Server(pool_bytes, slots, execute, poll)
+    results = srv.run(reqs)
+    torch.cuda.synchronize()
+    assert len(results) == len(reqs)
+    assert srv.max_in_flight > 1
+    for q, res in zip(reqs, results):
+        alone = mtb.mtb_align_stack(q.images, q.levels)
+        torch.cuda.synchronize()
+        assert torch.equal(res.shifts, alone["shifts"]), q.rid
+        assert torch.equal(res.errs, alone["errs"]), q.rid
+        assert res.completed >= res.admitted >= res.arrival - 1e-9
+    for r in specs[:: max(1, len(specs) // 5)]:
+        host = [np.ascontiguousarray(synth.serve_crop(base, r, i)) for i in range(r["n"])]
+        want = oracle.align_stack(host, r["levels"], ref_index=r["n"] // 2, threads=4)
+        got = results[r["rid"]]
+        assert np.array_equal(got.shifts.cpu().numpy(), want["shifts"]), r["rid"]
+        assert np.array_equal(got.errs.cpu().numpy().astype(np.int64), want["errs"]), r["rid"]

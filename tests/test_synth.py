@@ -69,3 +69,42 @@ def test_exposures_are_two_stops_apart():
     ratio = (hi / 255) ** 2.2 / np.maximum((lo / 255) ** 2.2, 1e-9)
     assert np.all(np.abs(ratio - 2.0) < 0.35)
     assert math.isclose(float(np.median(ratio)), 2.0, rel_tol=0.05)
+
+
+def test_serve_levels_formula():
+    assert synth.serve_levels(1225, 816) == 5       # 1 + floor(log2(816 / 32)) = 5
+    assert synth.serve_levels(8485, 5657) == 7      # capped at 7
+    assert synth.serve_levels(64, 64) == 2 and synth.serve_levels(63, 100) == 1
+
+
+def test_serve_requests_fit_the_base_and_are_reproducible():
+    reqs = synth.serve_requests(5, 200.0, 2.0, 8704, 5888)
+    again = synth.serve_requests(5, 200.0, 2.0, 8704, 5888)
+    assert reqs == again
+    assert 250 < len(reqs) < 550                    # Poisson(400)
+    arr = [r["arrival"] for r in reqs]
+    assert arr == sorted(arr) and arr[-1] < 2.0
+    for r in reqs:
+        W, H, L = r["width"], r["height"], r["levels"]
+        R = 1 << (L - 1)
+        assert 3 <= r["n"] <= 9 and L == synth.serve_levels(W, H)
+        assert 0.9e6 <= W * H <= 48.5e6
+        assert r["offsets"][r["n"] // 2] == (0, 0)
+        for (dx, dy), e in zip(r["offsets"], r["exposures"]):
+            assert -R <= dx <= R and -R <= dy <= R and 0 <= e < 9
+            assert 0 <= r["x0"] + dx and r["x0"] + dx + W <= 8704
+            assert 0 <= r["y0"] + dy and r["y0"] + dy + H <= 5888
+        assert r["exposures"][r["n"] // 2] == 4
+
+
+def test_serve_crop_is_a_translation():
+    base = [np.arange(40 * 30 * 3, dtype=np.int64).reshape(30, 40, 3) + 1000 * e for e in range(9)]
+    req = dict(offsets=[(2, -1), (0, 0), (-3, 2)], exposures=[3, 4, 5], x0=10, y0=8, width=12, height=9)
+    ref = synth.serve_crop(base, req, 1)
+    mov = synth.serve_crop(base, req, 2)
+    # aligned[y][x] = mov[y - dy][x - dx] with (dx, dy) = offset equals the reference scene.
+    dx, dy = req["offsets"][2]
+    for y in range(9):
+        for x in range(12):
+            if 0 <= y - dy < 9 and 0 <= x - dx < 12:
+                assert mov[y - dy, x - dx, 0] - 1000 == ref[y, x, 0]
