@@ -63,10 +63,13 @@ __device__ __forceinline__ uint32_t pack4(const uint32_t *v)
     return v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
 }
 
-// Level-0 histogram privatisation: kH0Copies copies per wave, lane l adding
-// into copy (l % kH0Copies); copies kHStride (odd) words apart, so that equal
-// values from lanes of different copies fall into different LDS banks.
-constexpr int kH0Copies = 4;
+// Level-0 histogram privatisation: kH0Copies copies per wave; copies kHStride
+// (odd) words apart, so that equal values from lanes of different copies fall
+// into different LDS banks.  Atomics to one address serialise, and nearby
+// pixels are often equal, so the lanes sharing a copy should hold pixels far
+// apart: lane (bx, by) (pixels at x = 16 bx + c, y = 4 by + r) adds into copy
+// (bx + 2 by) mod 8, whose lanes are at least 32 columns or 8 rows apart.
+constexpr int kH0Copies = 8;
 constexpr int kHStride = 257;
 
 // Loads one lane's 4 rows x 48 bytes (16 pixels) of RGB with 16-byte loads;
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     const int bx = lane & 15, by = lane >> 4;
     const Geometry &g = a.g;
     const int fused = g.L < kFused ? g.L : kFused;
-    uint32_t *h0 = hist0 + (wave * kH0Copies + (lane % kH0Copies)) * kHStride;
+    uint32_t *h0 = hist0 + (wave * kH0Copies + ((bx + 2 * by) & (kH0Copies - 1))) * kHStride;
 
     for (int i = tid; i < 4 * kH0Copies * kHStride; i += 256)
         hist0[i] = 0u;
@@ -457,16 +460,17 @@ __device__ __forceinline__ ChunkPos chunk_pos(const BitmapArgs &a, int64_t c, in
 
 __device__ __forceinline__ void load_chunk(const BitmapArgs &a, const ChunkPos &p, int lane, uint4 &v0, uint4 &v1)
 {
-    const uint8_t *src = a.pyr[p.img] + a.g.lv[p.level].gray_off + (int64_t)p.w0 * 64 + lane * 32;
+    const uint8_t *src = a.pyr[p.img] + a.g.lv[p.level].gray_off + (int64_t)p.w0 * 64 + lane * 16;
     const int bytes = p.cnt * 64;
-    v0 = lane * 32 < bytes ? ((const uint4 *)src)[0] : make_uint4(0u, 0u, 0u, 0u);
-    v1 = lane * 32 + 16 < bytes ? ((const uint4 *)src)[1] : make_uint4(0u, 0u, 0u, 0u);
+    v0 = lane * 16 < bytes ? *(const uint4 *)src : make_uint4(0u, 0u, 0u, 0u);
+    v1 = 1024 + lane * 16 < bytes ? *(const uint4 *)(src + 1024) : make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Each wavefront walks a contiguous run of chunks of kChunkWords = 32
-// consecutive 64-pixel words of one level.  Lane i loads bytes [32 i, 32 i +
-// 32) of the chunk (the next chunk's load is issued before the current one is
-// processed); the chunk is staged in LDS and read back byte-transposed
+// consecutive 64-pixel words of one level.  Lane i loads bytes [16 i, 16 i +
+// 16) and [1024 + 16 i, 1024 + 16 i + 16) of the chunk, so that each load
+// instruction covers 1 KB of whole lines (the next chunk's loads are issued
+// before the current one is processed); the chunk is staged in LDS and read back byte-transposed
 // (lane i <- byte 64 j + i), so that one ballot yields word j.  T words land
 // in lanes 0..31 and E words in lanes 32..63, and one store writes both.
 __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
@@ -505,8 +509,8 @@ __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
             ((int32_t *)(a.bm[cp.img] + g.med_off))[cp.level] = (int32_t)m;
 
         __builtin_amdgcn_wave_barrier();
-        stage[wave][2 * lane] = v0;
-        stage[wave][2 * lane + 1] = v1;
+        stage[wave][lane] = v0;
+        stage[wave][kWave + lane] = v1;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
