@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
     ap.add_argument("--serve-slots", type=int, default=4, help="served mode: stacks in flight at most")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--event-every", type=int, default=4,
+                    help="time the dominant kernel with HIP events in every N-th timed step")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum wall time of the CPU oracle sample")
@@ -313,8 +315,8 @@ def main():
         print("bench.py runs on exactly one GPU: the alignment path has no multi-GPU mode "
               "(stacks are independent; see DESIGN.md for how it would shard).", file=sys.stderr)
         sys.exit(2)
-    if args.steps < 1 or args.warmup < 0:
-        ap.error("--steps must be >= 1 and --warmup >= 0")
+    if args.steps < 1 or args.warmup < 0 or args.event_every < 1:
+        ap.error("--steps and --event-every must be >= 1 and --warmup >= 0")
 
     import numpy as np
     import torch
@@ -354,13 +356,15 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # Timed region: K whole-stack alignments; the dominant kernel is bracketed
-    # by HIP events on the launch stream.
+    # Timed region: K whole-stack alignments; in every --event-every-th step
+    # the dominant kernel carries HIP start/stop events on its launch stream
+    # (each evented launch costs a few microseconds of idle time around it).
     dominant = "k_pyramid"
     torch.cuda.synchronize()
     mtb.mtb_profile_begin(dominant)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        mtb.mtb_profile_pause(i % args.event_every != 0)
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -392,6 +396,7 @@ def main():
         "frac": round(achieved / PEAK_HBM_GBPS, 4),
         "traffic": load_traffic(dominant),
         "avg_launch_us": round(avg_s * 1e6, 2),
+        "evented_launches": launches,
         "algorithmic_bytes_per_launch": algo[dominant],
     }
 

@@ -232,7 +232,7 @@ mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32
  * name (launch count and summed event-to-event milliseconds) into h_out
  * (capacity entries), the number of entries into *h_count.
  * Errors: MTB_ERR_INVALID_ARG (begin while on / end while off / name of
- *         47 characters or more),
+ *         48 characters or more),
  *         MTB_ERR_WORKSPACE (more kernel names than capacity; the first
  *         capacity are still filled), MTB_ERR_DEVICE (an event failed).
  */
@@ -244,6 +244,15 @@ typedef struct mtb_kernel_time {
 
 mtb_status mtb_profile_begin(const char *kernel_name);
 mtb_status mtb_profile_end(mtb_kernel_time *h_out, int32_t capacity, int32_t *h_count);
+
+/*
+ * While profiling is on, mtb_profile_pause(1) stops bracketing new launches
+ * and mtb_profile_pause(0) resumes; events already recorded are kept for
+ * mtb_profile_end.  Nothing waits for the device.  Lets a benchmark time a
+ * sample of its launches without the events' cost on every one.
+ * Errors: MTB_ERR_INVALID_ARG when profiling is off.
+ */
+mtb_status mtb_profile_pause(int32_t paused);
 
 #ifdef __cplusplus
 }

@@ -39,6 +39,7 @@ __all__ = [
     "mtb_align_batch",
     "mtb_profile_begin",
     "mtb_profile_end",
+    "mtb_profile_pause",
 ]
 
 MTB_MAX_LEVELS = 16
@@ -149,6 +150,8 @@ def lib():
     L.mtb_batch_workspace_bytes.restype = sz
     L.mtb_align_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P]
     L.mtb_align_batch.restype = ctypes.c_int
+    L.mtb_profile_pause.argtypes = [i32]
+    L.mtb_profile_pause.restype = ctypes.c_int
     L.mtb_profile_begin.argtypes = [ctypes.c_char_p]
     L.mtb_profile_begin.restype = ctypes.c_int
     L.mtb_profile_end.argtypes = [ctypes.POINTER(_KernelTime), i32, ctypes.POINTER(i32)]
@@ -350,6 +353,11 @@ def mtb_align_batch(pairs, exclude_range: int = 4, workspace: torch.Tensor | Non
 def mtb_profile_begin(kernel_name: str | None = None) -> None:
     """Start timing the library's kernel launches on this thread (optionally one kernel name)."""
     _check("mtb_profile_begin", lib().mtb_profile_begin(None if kernel_name is None else kernel_name.encode()))
+
+
+def mtb_profile_pause(paused: bool) -> None:
+    """Stop (True) or resume (False) bracketing launches while profiling is on."""
+    _check("mtb_profile_pause", lib().mtb_profile_pause(1 if paused else 0))
 
 
 def mtb_profile_end(capacity: int = 64) -> dict:

@@ -10,6 +10,8 @@
 // The arithmetic is integer throughout; reductions are integer adds, so the
 // results do not depend on the order in which workgroups finish.
 
+#include <atomic>
+
 #include "mtb_internal.h"
 
 namespace mtb {
@@ -19,8 +21,10 @@ namespace {
 constexpr int kWave = 64;
 // Accelerator complex dies (XCDs) of the device, each with its own L2.
 constexpr int kXcds = 8;
-// Rows per batch of the fine search (rows per stream is a multiple of it).
-constexpr int kSearchBatch = 2;
+// Fine search: rows per batch and batches in flight per stream (rows per
+// stream, a power of two >= 4, is a multiple of their product).
+constexpr int kSearchBatch = 1;
+constexpr int kSearchDepth = 4;
 
 // Index of the calling wavefront in its workgroup, as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -428,16 +432,6 @@ __device__ uint32_t wave_median(const uint32_t *hist, uint32_t npix)
     return __shfl(v, f < 0 ? 0 : f);
 }
 
-// Writes the two 64-bit ballots t and e (as scalar halves) into lane j and
-// lane j + 32 of the word held in (lo, hi).  v_writelane reads its scalar
-// operands early, so the ballots (just written by VALU compares) are given
-// five wait states first.
-#define MTB_WRITELANES(lo, hi, t, e, j)                                                      \
-    asm volatile("s_nop 4\n\tv_writelane_b32 %0, %2, %6\n\tv_writelane_b32 %1, %3, %6\n\t"   \
-                 "v_writelane_b32 %0, %4, %7\n\tv_writelane_b32 %1, %5, %7"                    \
-                 : "+v"(lo), "+v"(hi)                                                        \
-                 : "s"((uint32_t)(t)), "s"((uint32_t)((t) >> 32)), "s"((uint32_t)(e)),         \
-                   "s"((uint32_t)((e) >> 32)), "i"(j), "i"((j) + 32))
 
 struct ChunkPos {
     int img, level, w0, cnt;
@@ -458,24 +452,63 @@ __device__ __forceinline__ ChunkPos chunk_pos(const BitmapArgs &a, int64_t c, in
     return p;
 }
 
+// Lane i's 32 pixels of a chunk: bytes [32 i, 32 i + 32), zero past the chunk.
 __device__ __forceinline__ void load_chunk(const BitmapArgs &a, const ChunkPos &p, int lane, uint4 &v0, uint4 &v1)
 {
-    const uint8_t *src = a.pyr[p.img] + a.g.lv[p.level].gray_off + (int64_t)p.w0 * 64 + lane * 16;
-    const int bytes = p.cnt * 64;
-    v0 = lane * 16 < bytes ? *(const uint4 *)src : make_uint4(0u, 0u, 0u, 0u);
-    v1 = 1024 + lane * 16 < bytes ? *(const uint4 *)(src + 1024) : make_uint4(0u, 0u, 0u, 0u);
+    const uint8_t *src = a.pyr[p.img] + a.g.lv[p.level].gray_off + (int64_t)p.w0 * 64 + lane * 32;
+    const bool in = lane < 2 * p.cnt;
+    v0 = in ? ((const uint4 *)src)[0] : make_uint4(0u, 0u, 0u, 0u);
+    v1 = in ? ((const uint4 *)src)[1] : make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Byte-wise x >= y for a uniform threshold y in [0, 255], four bytes at once;
+// the answer is bit 7 of each byte (the other bits are undefined).  With
+// xh = x | 0x80808080 and low = (y & 0x7f) * 0x01010101, each byte of xh - low
+// is 0x80 + (x & 0x7f) - (y & 0x7f), in [1, 255], so no byte borrows from the
+// next and its bit 7 is [x & 0x7f >= y & 0x7f].  Bit 7 of x and y decides the
+// rest: y < 128 (sel all ones) gives x7 | d7, y >= 128 (sel 0) gives x7 & d7.
+struct ByteGe {
+    uint32_t low, sel;
+};
+__device__ __forceinline__ ByteGe byte_ge(uint32_t y)
+{
+    return ByteGe{(y & 0x7fu) * 0x01010101u, y < 128u ? ~0u : 0u};
+}
+__device__ __forceinline__ uint32_t ge_bytes(uint32_t x, uint32_t xh, ByteGe c)
+{
+    const uint32_t d = xh - c.low;
+    return (x & d) | (c.sel & (x | d));
+}
+
+// Eight dwords d[k] holding pixels 4k .. 4k+3 (byte b = pixel 4k + b) are
+// transposed so that t[k] holds pixels k, k+8, k+16, k+24 (byte b = pixel 8b + k).
+// v_perm_b32 (__builtin_amdgcn_perm(hi, lo, sel)): selector byte values 0-3
+// pick bytes of lo, 4-7 bytes of hi.
+__device__ __forceinline__ void transpose8(const uint32_t *d, uint32_t *t)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // h = 0: dwords 0,2,4,6 -> t[0..3]; h = 1: 1,3,5,7 -> t[4..7]
+        const uint32_t A = __builtin_amdgcn_perm(d[2 + h], d[0 + h], 0x05010400u);  // d0.b0 d2.b0 d0.b1 d2.b1
+        const uint32_t B = __builtin_amdgcn_perm(d[2 + h], d[0 + h], 0x07030602u);  // d0.b2 d2.b2 d0.b3 d2.b3
+        const uint32_t C = __builtin_amdgcn_perm(d[6 + h], d[4 + h], 0x05010400u);  // d4.b0 d6.b0 d4.b1 d6.b1
+        const uint32_t D = __builtin_amdgcn_perm(d[6 + h], d[4 + h], 0x07030602u);  // d4.b2 d6.b2 d4.b3 d6.b3
+        t[4 * h + 0] = __builtin_amdgcn_perm(C, A, 0x05040100u);
+        t[4 * h + 1] = __builtin_amdgcn_perm(C, A, 0x07060302u);
+        t[4 * h + 2] = __builtin_amdgcn_perm(D, B, 0x05040100u);
+        t[4 * h + 3] = __builtin_amdgcn_perm(D, B, 0x07060302u);
+    }
 }
 
 // Each wavefront walks a contiguous run of chunks of kChunkWords = 32
-// consecutive 64-pixel words of one level.  Lane i loads bytes [16 i, 16 i +
-// 16) and [1024 + 16 i, 1024 + 16 i + 16) of the chunk, so that each load
-// instruction covers 1 KB of whole lines (the next chunk's loads are issued
-// before the current one is processed); the chunk is staged in LDS and read back byte-transposed
-// (lane i <- byte 64 j + i), so that one ballot yields word j.  T words land
-// in lanes 0..31 and E words in lanes 32..63, and one store writes both.
+// consecutive 64-pixel words of one level (the next chunk's loads are issued
+// before the current one is processed).  Lane i takes the chunk's bytes
+// [32 i, 32 i + 32), i.e. half-word i of the chunk, and forms its 32 T and E
+// bits in registers: four pixels per dword compared at once (ByteGe), after a
+// byte transpose that lets the per-byte answers be gathered into bit order
+// with one shift and one and-or per dword.  Lane i then stores dword i of the
+// chunk's T words and of its E words.
 __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
 {
-    __shared__ uint4 stage[4][2 * kWave];
     const int wave = wave_id();
     const int lane = threadIdx.x & 63;
     const Geometry &g = a.g;
@@ -489,10 +522,11 @@ __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
     if (c0 >= c1)
         return;
     const uint32_t X = (uint32_t)a.exclude;
-    const uint8_t *st = (const uint8_t *)&stage[wave][0];
 
     int cur_img = -1, cur_l = -1;
     uint32_t m = 0;
+    ByteGe ge_t = byte_ge(0), ge_hi = byte_ge(0), ge_lo = byte_ge(0);
+    uint32_t keep_t = 0, keep_hi = 0;
     ChunkPos p = chunk_pos(a, c0, per_image);
     uint4 v0, v1;
     load_chunk(a, p, lane, v0, v1);
@@ -504,50 +538,41 @@ __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
                             (uint32_t)(lv.w * lv.h));
             cur_img = cp.img;
             cur_l = cp.level;
+            // T = [g >= m + 1]; E = [g >= m + X + 1] | ~[g >= max(m - X, 0)].
+            // A threshold above 255 is never reached: its bits are cleared.
+            ge_t = byte_ge(m + 1u);
+            keep_t = m < 255u ? ~0u : 0u;
+            ge_hi = byte_ge(m + X + 1u);
+            keep_hi = m + X < 255u ? ~0u : 0u;
+            ge_lo = byte_ge(m > X ? m - X : 0u);
         }
         if (cp.w0 == 0 && lane == 0)
             ((int32_t *)(a.bm[cp.img] + g.med_off))[cp.level] = (int32_t)m;
 
-        __builtin_amdgcn_wave_barrier();
-        stage[wave][lane] = v0;
-        stage[wave][kWave + lane] = v1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
+        const uint32_t d[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
         if (c + 1 < c1) {
             p = chunk_pos(a, c + 1, per_image);
             load_chunk(a, p, lane, v0, v1);
         }
-
-        uint32_t out_lo = 0, out_hi = 0;
-        const uint32_t ebias = X - m;
-        uint32_t gvs[kChunkWords];  // all reads issued before the first use
+        uint32_t t[8];
+        transpose8(d, t);
+        uint32_t tw = 0, ew = 0;
 #pragma unroll
-        for (int j = 0; j < kChunkWords; ++j)
-            gvs[j] = st[j * 64 + lane];
-#pragma unroll
-        for (int j = 0; j < kChunkWords; ++j) {
-            if (j < cp.cnt) {
-                const uint64_t tw = ballot(gvs[j] > m);
-                const uint64_t ew = ballot(gvs[j] + ebias > 2u * X);
-                MTB_WRITELANES(out_lo, out_hi, tw, ew, j);
-            }
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t xh = t[k] | 0x80808080u;
+            const uint32_t rt = ge_bytes(t[k], xh, ge_t) & keep_t;
+            const uint32_t re = (ge_bytes(t[k], xh, ge_hi) & keep_hi) | ~ge_bytes(t[k], xh, ge_lo);
+            // Bit 7 of byte b is pixel 8b + k: move it to bit 8b + k.
+            tw |= (rt >> (7 - k)) & (0x01010101u << k);
+            ew |= (re >> (7 - k)) & (0x01010101u << k);
         }
-        // Bits past the level width are zero: lane i holds word w0 + i % 32, whose
-        // pixels start at column 64 * ((w0 + i % 32) mod wpr).
-        const int nbits = lv.w - 64 * ((cp.w0 + (lane & 31)) % lv.wpr);
-        if (nbits < 64) {
-            const uint64_t keep = nbits <= 0 ? 0ull : ((1ull << nbits) - 1ull);
-            out_lo &= (uint32_t)keep;
-            out_hi &= (uint32_t)(keep >> 32);
-        }
-        const uint64_t word = ((uint64_t)out_hi << 32) | out_lo;
-        if (lane < 32) {
-            if (lane < cp.cnt)
-                ((uint64_t *)(a.bm[cp.img] + lv.tb_off))[cp.w0 + lane] = word;
-        } else if (lane - 32 < cp.cnt) {
-            ((uint64_t *)(a.bm[cp.img] + lv.eb_off))[cp.w0 + lane - 32] = word;
+        // Bits past the level width are zero: lane i holds half-word i % 2 of
+        // word w0 + i / 2, whose pixels start at column 64 * ((w0 + i / 2) mod wpr).
+        const int nbits = lv.w - 64 * ((cp.w0 + (lane >> 1)) % lv.wpr) - 32 * (lane & 1);
+        const uint32_t keep = nbits >= 32 ? ~0u : (nbits <= 0 ? 0u : (1u << nbits) - 1u);
+        if (lane < 2 * cp.cnt) {
+            ((uint32_t *)(a.bm[cp.img] + lv.tb_off))[2 * (int64_t)cp.w0 + lane] = tw & keep;
+            ((uint32_t *)(a.bm[cp.img] + lv.eb_off))[2 * (int64_t)cp.w0 + lane] = ew & keep;
         }
     }
 }
@@ -682,7 +707,9 @@ __device__ void search_unit_t(const uint8_t *ref, const uint8_t *mov, const Leve
             const uint32_t base = (uint32_t)yy * (uint32_t)row_bytes + kref;
             b.rt[i] = *(const uint2 *)(tr + base);
             b.re[i] = *(const uint2 *)(er + base);
-            load_moving(y + i - by + 1, b.mt[i], b.me[i]);
+            // Past the stream's last row this re-reads that row's moving words
+            // (cache hits); they are never scored.
+            load_moving(yy - by + 1, b.mt[i], b.me[i]);
         }
     };
 
@@ -725,33 +752,33 @@ __device__ void search_unit_t(const uint8_t *ref, const uint8_t *mov, const Leve
         }
     };
 
-    RowBatch<kB, kW> b0, b1;
+    // kP batches in a ring: while one is scored, the loads of the next kP - 1
+    // are in flight.  Loads past the stream's rows are clamped to its last
+    // row (valid addresses, cache hits) so that no load sits behind a branch;
+    // the only branch, at the end of a round, is uniform (rows is).
+    constexpr int kP = kSearchDepth;
+    RowBatch<kB, kW> b[kP];
     {
         uint32_t w[4][kW], m[2][kW];
         load_moving(y_begin - by - 1, w[0], w[1]);
         load_moving(y_begin - by, w[2], w[3]);
-        load(y_begin, b0);
+#pragma unroll
+        for (int k = 0; k < kP - 1; ++k)
+            load(y_begin + k * kB, b[k]);
         mask_moving(y_begin - by - 1, w[1], m[0]);
         mask_moving(y_begin - by, w[3], m[1]);
         shift_row(w[0], m[0], at, ae);
         shift_row(w[2], m[1], bt, be);
     }
-    // Every branch below is uniform (rows is); each batch's loads are issued
-    // in the same block as the scoring of the batch before.
-    for (int i = 0;; i += 2 * kB) {
+    for (int i = 0;; i += kP * kB) {
         const int y = y_begin + i;
-        if (i + kB >= rows) {
-            score(b0, y);
-            break;
+#pragma unroll
+        for (int k = 0; k < kP; ++k) {
+            load(y + (k + kP - 1) * kB, b[(k + kP - 1) % kP]);
+            score(b[k], y + k * kB);
         }
-        load(y + kB, b1);
-        score(b0, y);
-        if (i + 2 * kB >= rows) {
-            score(b1, y + kB);
+        if (i + kP * kB >= rows)
             break;
-        }
-        load(y + 2 * kB, b0);
-        score(b1, y + kB);
     }
 }
 
@@ -1172,6 +1199,23 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
 
 // ---------------------------------------------------------------- launchers
 
+// Workgroups of 256 threads of `kernel` that fit on one compute unit at once
+// (registers and LDS), from the runtime's occupancy calculator; cached.
+template <typename A>
+int resident_per_cu(void (*kernel)(A))
+{
+    static std::atomic<int> cached{0};
+    int v = cached.load(std::memory_order_relaxed);
+    if (v == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, 256, 0) != hipSuccess || n < 1)
+            n = 1;
+        cached.store(n, std::memory_order_relaxed);
+        v = n;
+    }
+    return v;
+}
+
 hipError_t launch_zero(const ZeroArgs &a, hipStream_t s)
 {
     if (a.count <= 0)
@@ -1190,10 +1234,10 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     a.tiles_x = (a.g.W + kTileW - 1) / kTileW;
     a.tiles_y = (a.g.H + kTileH - 1) / kTileH;
     const int64_t total = (int64_t)a.tiles_x * a.tiles_y * a.n;
-    // Three workgroups fit on a compute unit at this kernel's register count;
-    // each XCD gets the same number of slots (see k_pyramid).
+    // One round of resident workgroups; each XCD gets the same number of
+    // slots (see k_pyramid).
     const int64_t share = (total + kXcds - 1) / kXcds;
-    int64_t slots = (int64_t)cus * 3 / kXcds;
+    int64_t slots = (int64_t)cus * resident_per_cu(k_pyramid) / kXcds;
     slots = slots > share ? share : (slots < 1 ? 1 : slots);
     a.xcd_tiles = (int32_t)share;
     const int blocks = (int)(slots * kXcds);
@@ -1213,7 +1257,7 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
 {
     const int64_t total = a.chunk_start[a.g.L] * a.n;
     int64_t blocks = (total + 3) / 4;
-    const int64_t cap = (int64_t)cus * 8;
+    const int64_t cap = (int64_t)cus * resident_per_cu(k_bitmaps);
     blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
     return launch_kernel("k_bitmaps", k_bitmaps, dim3((unsigned)blocks), dim3(256), s, a);
 }
@@ -1244,12 +1288,12 @@ hipError_t launch_search(SearchArgs a, int cus, hipStream_t s)
     auto row_blocks = [&](int l, int rows) {
         return ((plan_level(g.lv[l], rows).units + 3) / 4 + kXcds - 1) / kXcds * kXcds;
     };
+    const int64_t resident = (int64_t)cus * resident_per_cu(k_search_fine);
     for (int l = g.L - 1 - cn; l >= 0; --l) {
         // Rows per stream: the fewest (at least 4) that keep the grid within one
-        // round of resident workgroups (three per compute unit at this kernel's
-        // register count), so no workgroup waits for another to finish.
+        // round of resident workgroups, so no workgroup waits for another to finish.
         int rows = 4;
-        while (rows < 64 && (int64_t)row_blocks(l, rows) * a.npairs > (int64_t)cus * 3)
+        while (rows < 64 && (int64_t)row_blocks(l, rows) * a.npairs > resident)
             rows <<= 1;
         a.level = l;
         a.rows_per_stream = rows;

@@ -22,6 +22,7 @@ struct Record {
 };
 
 thread_local bool t_enabled = false;
+thread_local bool t_paused = false;
 thread_local char t_filter[48] = {0};  // empty: every kernel
 thread_local std::vector<Record> t_records;
 thread_local hipError_t t_error = hipSuccess;
@@ -65,7 +66,7 @@ void give_event(hipEvent_t e)
 ProfEvents prof_take(const char *name)
 {
     ProfEvents ev;
-    if (!t_enabled || (t_filter[0] && strcmp(t_filter, name) != 0))
+    if (!t_enabled || t_paused || (t_filter[0] && strcmp(t_filter, name) != 0))
         return ev;
     hipError_t r = hipSuccess;
     ev.start = take_event(&r);
@@ -108,6 +109,15 @@ mtb_status mtb_profile_begin(const char *kernel_name)
     t_records.clear();
     t_error = hipSuccess;
     t_enabled = true;
+    t_paused = false;
+    return MTB_OK;
+}
+
+mtb_status mtb_profile_pause(int32_t paused)
+{
+    if (!t_enabled)
+        return MTB_ERR_INVALID_ARG;
+    t_paused = paused != 0;
     return MTB_OK;
 }
 
@@ -116,6 +126,7 @@ mtb_status mtb_profile_end(mtb_kernel_time *h_out, int32_t capacity, int32_t *h_
     if (!t_enabled)
         return MTB_ERR_INVALID_ARG;
     t_enabled = false;
+    t_paused = false;
     mtb_status status = t_error == hipSuccess ? MTB_OK : MTB_ERR_DEVICE;
     int32_t count = 0;
     for (const Record &r : t_records) {

@@ -234,3 +234,19 @@ def test_batch_validation(mtb):
         setattr(broken[1], field, value)
         assert L.mtb_batch_workspace_bytes(broken, 2) == 0, field
         assert L.mtb_align_batch(broken, 2, 4, FAKE, ws, FAKE, FAKE, NULL) == 1, field
+
+
+def test_profile_state_machine(mtb):
+    L = _c(mtb)
+    from paper_2007_06483_amd import _KernelTime
+
+    out = (_KernelTime * 4)()
+    cnt = ctypes.c_int32(-1)
+    assert L.mtb_profile_pause(1) == 1              # profiling is off
+    assert L.mtb_profile_end(out, 4, ctypes.byref(cnt)) == 1
+    assert L.mtb_profile_begin(b"x" * 48) == 1      # name too long
+    assert L.mtb_profile_begin(b"k_pyramid") == 0
+    assert L.mtb_profile_begin(None) == 1           # already on
+    assert L.mtb_profile_pause(1) == 0 and L.mtb_profile_pause(0) == 0
+    assert L.mtb_profile_end(out, 4, ctypes.byref(cnt)) == 0 and cnt.value == 0
+    assert L.mtb_profile_pause(0) == 1

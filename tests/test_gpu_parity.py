@@ -50,14 +50,14 @@ def _strided_dev(img, extra, offset):
     return torch.as_strided(d, (h, w, 3), (stride, 3, 1), offset)
 
 
-def _check_pyramid(mtb, d_img, img, L):
+def _check_pyramid(mtb, d_img, img, L, exclude=4):
     h, w, _ = img.shape
     lay = mtb.mtb_get_layout(w, h, L)
     pyr = mtb.mtb_build_pyramid(d_img, L)
-    bm = mtb.mtb_bitmaps(pyr, w, h, L, 4)
+    bm = mtb.mtb_bitmaps(pyr, w, h, L, exclude)
     torch.cuda.synchronize()
     pyr_h, bm_h = pyr.cpu().numpy(), bm.cpu().numpy()
-    want = oracle.pyramid(img, L)
+    want = oracle.pyramid(img, L, exclude)
     for l, g in enumerate(gray_levels(pyr_h, lay)):
         assert np.array_equal(g, want.gray(l)), f"gray level {l}"
     assert np.array_equal(histograms(pyr_h, lay), want.hist)
@@ -95,6 +95,18 @@ def test_scene_pyramid_matches_oracle(mtb, w, h, L):
 def test_pyramid_with_unaligned_rows(mtb, extra, offset):
     img = _noise(77, 133, 42 + extra)
     _check_pyramid(mtb, _strided_dev(img, extra, offset), img, 5)
+
+
+@pytest.mark.parametrize("exclude", [0, 1, 7, 127, 200, 255])
+def test_bitmaps_exclusion_ranges(mtb, exclude):
+    # Thresholds m + X + 1 above 255 and m - X below 0 (the band covers the whole range).
+    img = _noise(67, 150, 40 + exclude)
+    img[:20] = 250
+    img[20:30] = 3
+    _check_pyramid(mtb, _to_dev(img), img, 4, exclude)
+    for val in (0, 255):
+        flat = np.full((40, 70, 3), val, np.uint8)
+        _check_pyramid(mtb, _to_dev(flat), flat, 3, exclude)
 
 
 def test_saturated_and_flat_images(mtb):
