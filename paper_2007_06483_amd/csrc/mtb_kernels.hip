@@ -22,7 +22,7 @@ constexpr int kWave = 64;
 // Accelerator complex dies (XCDs) of the device, each with its own L2.
 constexpr int kXcds = 8;
 // Fine search: rows per batch and batches in flight per stream (rows per
-// stream, a power of two >= 4, is a multiple of their product).
+// stream is a multiple of their product).
 constexpr int kSearchBatch = 1;
 constexpr int kSearchDepth = 4;
 
@@ -1290,11 +1290,14 @@ hipError_t launch_search(SearchArgs a, int cus, hipStream_t s)
     };
     const int64_t resident = (int64_t)cus * resident_per_cu(k_search_fine);
     for (int l = g.L - 1 - cn; l >= 0; --l) {
-        // Rows per stream: the fewest (at least 4) that keep the grid within one
-        // round of resident workgroups, so no workgroup waits for another to finish.
-        int rows = 4;
+        // Rows per stream: the fewest (a multiple of the batches in flight)
+        // that keep the grid within one round of resident workgroups, so that
+        // every compute unit holds about as many workgroups as it can run and
+        // none waits for another to finish.
+        constexpr int kStep = kSearchBatch * kSearchDepth;
+        int rows = kStep;
         while (rows < 64 && (int64_t)row_blocks(l, rows) * a.npairs > resident)
-            rows <<= 1;
+            rows += kStep;
         a.level = l;
         a.rows_per_stream = rows;
         const int blocks = row_blocks(l, rows);
