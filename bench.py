@@ -218,6 +218,62 @@ def run_batch(args, mtb, synth, torch, np, dev):
     print(json.dumps(result), flush=True)
 
 
+def run_apply(args, mtb, synth, torch, np, dev):
+    """Translating the 7 x 6000x4000 stack by its shifts (zero fill), after aligning it once."""
+    import oracle
+
+    log("generating stack7_6000x4000 ...")
+    w = synth.workload("stack7_6000x4000")
+    (imgs, _, ref), = w.stacks
+    n, W, H = len(imgs), w.width, w.height
+    d = [torch.from_numpy(im).to(dev) for im in imgs]
+    shifts = mtb.mtb_align_stack(d, w.levels, ref_index=ref)["shifts"]
+    outs = [torch.empty((H, W, 3), dtype=torch.uint8, device=dev) for _ in range(n)]
+
+    def step():
+        mtb.mtb_apply_shifts(d, shifts, 0, out=outs)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mtb.mtb_profile_begin("k_apply")
+    t = time.perf_counter()
+    for i in range(args.steps):
+        mtb.mtb_profile_pause(i % args.event_every != 0)
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    launches, total_ms = mtb.mtb_profile_end()["k_apply"]
+    algo = n * 6 * W * H  # RGB read + RGB written
+    achieved = algo / (total_ms / launches / 1e3) / 1e9
+    mp = n * W * H / 1e6
+    sh = shifts.cpu().numpy()
+    same = all(np.array_equal(outs[k].cpu().numpy(), oracle.apply_shift(imgs[k], int(sh[k][0]), int(sh[k][1]), 0))
+               for k in range(n))
+    result = {
+        "metric": METRIC, "value": round(mp / (ms / 1e3), 1), "unit": "MP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "apply7_6000x4000", "images": n, "width": W, "height": H, "fill": "zero"},
+        "roofline": {"bound": "hbm", "kernel": "k_apply", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "avg_launch_us": round(total_ms / launches * 1e3, 2), "algorithmic_bytes_per_launch": algo},
+        "parity_vs_oracle": bool(same),
+    }
+    if not args.no_cpu_baseline:
+        reps, t = 0, time.perf_counter()
+        while True:
+            for k in range(n):
+                oracle.apply_shift(imgs[k], int(sh[k][0]), int(sh[k][1]), 0)
+            reps += 1
+            dt = time.perf_counter() - t
+            if dt >= args.cpu_seconds:
+                break
+        result["cpu_baseline"] = {"value": round(reps * mp / dt, 3), "unit": "MP/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"{reps} translations of the 7-image stack in {dt:.2f} s, one thread"}
+    print(json.dumps(result), flush=True)
+
+
 def run_served(args, mtb, synth, torch, np, dev):
     """Poisson arrivals of exposure stacks served with continuous batching (device-staged:
     the requests are crops of a base scene resident on the GPU)."""
@@ -297,7 +353,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stack7_6000x4000",
                     choices=["stack7_6000x4000", "pair_4096x3072", "pair_512x384", "batch64_uneven",
-                             "served_poisson200"])
+                             "served_poisson200", "apply7_6000x4000"])
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
     ap.add_argument("--serve-slots", type=int, default=4, help="served mode: stacks in flight at most")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -333,6 +389,8 @@ def main():
         return run_batch(args, mtb, synth, torch, np, dev)
     if args.workload == "served_poisson200":
         return run_served(args, mtb, synth, torch, np, dev)
+    if args.workload == "apply7_6000x4000":
+        return run_apply(args, mtb, synth, torch, np, dev)
 
     log(f"generating {args.workload} ...")
     t0 = time.perf_counter()

@@ -184,6 +184,26 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
                            uint32_t *d_trace, void *stream);
 
 /*
+ * Translates every image of a stack by its shift (Section III-B: the shift
+ * found for an exposure is applied to it, bringing it onto the reference):
+ *   out_i[y][x] = in_i[y - dy_i][x - dx_i]   (all three channels)
+ * Where (x - dx_i, y - dy_i) falls outside the image the paper says nothing;
+ * `fill` chooses zeros (MTB_FILL_ZERO) or the nearest edge pixel
+ * (MTB_FILL_EDGE, coordinates clamped into the image).
+ *   h_d_rgb          host array of n device pointers, the input images (as for mtb_align_stack)
+ *   d_shifts         device int32[n][2]: (dx, dy) per image, e.g. mtb_align_stack's d_shifts
+ *   h_d_out          host array of n device pointers: height rows of out_stride bytes each;
+ *                    bytes past 3 * width of a row are not written; must not overlap the inputs
+ *   out_stride       >= 3 * width
+ * Errors: MTB_ERR_INVALID_ARG (null pointers, sizes, strides, fill, n), MTB_ERR_DEVICE.
+ */
+#define MTB_FILL_ZERO 0
+#define MTB_FILL_EDGE 1
+mtb_status mtb_apply_shifts(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
+                            int64_t row_stride, const int32_t *d_shifts, int32_t fill,
+                            uint8_t *const *h_d_out, int64_t out_stride, void *stream);
+
+/*
  * One item of a batch: a reference and a moving RGB image of the same size
  * and row stride (see Images above), aligned with `levels` levels.
  */

@@ -28,6 +28,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 __all__ = [
+    "apply_shift",
     "build",
     "gray",
     "downsample",
@@ -89,6 +90,8 @@ def _load():
     lib.oracle_search.restype = None
     lib.oracle_align_pair.argtypes = [P, P, i32, i32, i64, i32, i32, P, P, P, P]
     lib.oracle_align_pair.restype = i32
+    lib.oracle_apply_shift.argtypes = [P, i32, i32, i64, i32, i32, i32, P, i64]
+    lib.oracle_apply_shift.restype = None
     _lib = lib
     return lib
 
@@ -255,4 +258,13 @@ def align_stack(images, levels: int, ref_index: int | None = None, exclude: int 
     out = {"shifts": shifts, "errs": errs, "ref_index": ref, "pairs": res}
     if keep:
         out["pyramids"] = pyrs
+    return out
+
+
+def apply_shift(img: np.ndarray, dx: int, dy: int, fill: int = 0) -> np.ndarray:
+    """out[y][x] = img[y - dy][x - dx]; outside the image: zeros (fill 0) or the
+    nearest edge pixel (fill 1).  Returns a packed (H, W, 3) image."""
+    a, W, H, s = _rgb(img)
+    out = np.empty((H, W, 3), np.uint8)
+    _load().oracle_apply_shift(_ptr(a), W, H, s, int(dx), int(dy), int(fill), _ptr(out), 3 * W)
     return out

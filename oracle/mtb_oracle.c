@@ -255,3 +255,34 @@ int32_t oracle_align_pair(const uint8_t *rgb_ref, const uint8_t *rgb_mov, int32_
     free(med);
     return 0;
 }
+
+/*
+ * Applying the found shift to a moving image (Section III-B: once the shift is
+ * known the image is translated by it; Section III-A: the shift moves the
+ * moving image onto the reference).  out[y][x] = in[y - dy][x - dx] for every
+ * channel; where (x - dx, y - dy) falls outside the image the paper says
+ * nothing, and two readings are offered: fill 0 writes zero bytes, fill 1
+ * repeats the nearest edge pixel (coordinates clamped into the image).
+ * Output rows are out_stride bytes apart; bytes past 3 * width are untouched.
+ */
+void oracle_apply_shift(const uint8_t *in, int32_t width, int32_t height, int64_t stride,
+                        int32_t dx, int32_t dy, int32_t fill, uint8_t *out, int64_t out_stride)
+{
+    for (int32_t y = 0; y < height; ++y) {
+        for (int32_t x = 0; x < width; ++x) {
+            int64_t sx = (int64_t)x - dx, sy = (int64_t)y - dy;
+            const int inside = sx >= 0 && sx < width && sy >= 0 && sy < height;
+            for (int c = 0; c < 3; ++c) {
+                uint8_t v = 0;
+                if (inside) {
+                    v = in[sy * stride + 3 * sx + c];
+                } else if (fill == 1) {
+                    const int64_t cx = sx < 0 ? 0 : (sx >= width ? width - 1 : sx);
+                    const int64_t cy = sy < 0 ? 0 : (sy >= height ? height - 1 : sy);
+                    v = in[cy * stride + 3 * cx + c];
+                }
+                out[(int64_t)y * out_stride + 3 * (int64_t)x + c] = v;
+            }
+        }
+    }
+}

@@ -35,6 +35,9 @@ __all__ = [
     "mtb_bitmaps",
     "mtb_align_pair",
     "mtb_align_stack",
+    "mtb_apply_shifts",
+    "MTB_FILL_ZERO",
+    "MTB_FILL_EDGE",
     "mtb_batch_workspace_bytes",
     "mtb_align_batch",
     "mtb_profile_begin",
@@ -45,6 +48,8 @@ __all__ = [
 MTB_MAX_LEVELS = 16
 MTB_MAX_STACK = 32
 MTB_MAX_BATCH = 4096
+MTB_FILL_ZERO = 0
+MTB_FILL_EDGE = 1
 
 MTB_OK = 0
 STATUS_NAMES = {0: "MTB_OK", 1: "MTB_ERR_INVALID_ARG", 2: "MTB_ERR_WORKSPACE",
@@ -146,6 +151,8 @@ def lib():
     L.mtb_align_pair.restype = ctypes.c_int
     L.mtb_align_stack.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, i32, i32, P, sz, P, P, P, P]
     L.mtb_align_stack.restype = ctypes.c_int
+    L.mtb_apply_shifts.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, P, i32, ctypes.POINTER(P), i64, P]
+    L.mtb_apply_shifts.restype = ctypes.c_int
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
     L.mtb_batch_workspace_bytes.restype = sz
     L.mtb_align_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P]
@@ -306,6 +313,38 @@ def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int 
                                  _ptr(workspace), workspace.numel(), _ptr(shifts), _ptr(errs),
                                  _ptr(tr), _stream(stream)))
     return {"shifts": shifts, "errs": errs, "trace": tr, "workspace": workspace}
+
+
+def mtb_apply_shifts(images, shifts: torch.Tensor, fill: int = MTB_FILL_ZERO, out=None,
+                     stream=None) -> list:
+    """Translate every (H, W, 3) image by its row of ``shifts`` (device int32[n][2]).
+
+    Returns the output images (new packed tensors unless ``out`` gives them).
+    """
+    n = len(images)
+    if not 1 <= n <= MTB_MAX_STACK:
+        raise ValueError(f"a stack holds 1..{MTB_MAX_STACK} images")
+    W, H, stride = _rgb_geometry(images[0])
+    for im in images:
+        if _rgb_geometry(im) != (W, H, stride):
+            raise ValueError("all images must share size and stride")
+    if (not isinstance(shifts, torch.Tensor) or not shifts.is_cuda or shifts.dtype != torch.int32
+            or tuple(shifts.shape) != (n, 2) or not shifts.is_contiguous()):
+        raise ValueError("shifts must be a contiguous int32 device tensor of shape (n, 2)")
+    if out is None:
+        out = [torch.empty((H, W, 3), dtype=torch.uint8, device=images[0].device) for _ in range(n)]
+    ostride = None
+    for o in out:
+        ow, oh, os_ = _rgb_geometry(o)
+        if (ow, oh) != (W, H) or (ostride is not None and os_ != ostride):
+            raise ValueError("outputs must match the inputs' size and share a stride")
+        ostride = os_
+    ins = (ctypes.c_void_p * n)(*[im.data_ptr() for im in images])
+    outs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in out])
+    _check("mtb_apply_shifts",
+           lib().mtb_apply_shifts(ins, n, W, H, stride, _ptr(shifts), int(fill), outs, ostride,
+                                  _stream(stream)))
+    return out
 
 
 def _batch_items(pairs):

@@ -486,6 +486,39 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
     return device_status(enqueue_set(ps, g, row_stride, align, exclude_range, ws, out, z, cus, s));
 }
 
+mtb_status mtb_apply_shifts(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
+                            int64_t row_stride, const int32_t *d_shifts, int32_t fill,
+                            uint8_t *const *h_d_out, int64_t out_stride, void *stream)
+{
+    if (!h_d_rgb || !h_d_out || !d_shifts || n < 1 || n > kMaxStack || width < 1 || height < 1 ||
+        (int64_t)width * height >= ((int64_t)1 << 31))
+        return MTB_ERR_INVALID_ARG;
+    if (row_stride < 3 * (int64_t)width || out_stride < 3 * (int64_t)width || (fill != 0 && fill != 1))
+        return MTB_ERR_INVALID_ARG;
+    ApplyArgs a;
+    memset(&a, 0, sizeof(a));
+    bool aligned = row_stride % 4 == 0 && out_stride % 16 == 0;
+    for (int i = 0; i < n; ++i) {
+        if (!h_d_rgb[i] || !h_d_out[i])
+            return MTB_ERR_INVALID_ARG;
+        a.rgb[i] = h_d_rgb[i];
+        a.out[i] = h_d_out[i];
+        aligned = aligned && (uintptr_t)h_d_rgb[i] % 4 == 0 && (uintptr_t)h_d_out[i] % 16 == 0;
+    }
+    const int cus = current_device_cus();
+    if (cus <= 0)
+        return MTB_ERR_UNSUPPORTED;
+    a.shifts = d_shifts;
+    a.stride = row_stride;
+    a.out_stride = out_stride;
+    a.n = n;
+    a.width = width;
+    a.height = height;
+    a.fill = fill;
+    a.aligned = aligned ? 1 : 0;
+    return device_status(launch_apply(a, cus, (hipStream_t)stream));
+}
+
 size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items)
 {
     if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH)

@@ -131,6 +131,20 @@ struct SearchArgs {
     Geometry g;
 };
 
+// ------------------------------------------------------------------ apply shifts
+
+// Translating each image of a stack by its shift (out[y][x] = in[y - dy][x - dx]).
+struct ApplyArgs {
+    const uint8_t *rgb[kMaxStack];
+    uint8_t *out[kMaxStack];
+    const int32_t *shifts;  // device int32[n][2]
+    int64_t stride, out_stride;
+    int32_t n, width, height;
+    int32_t fill;           // 0: zeros outside the image, 1: nearest edge pixel
+    int32_t aligned;        // input rows 4-byte aligned and output rows 16-byte aligned
+    int32_t pad_;
+};
+
 struct ZeroArgs {
     uint32_t *ptr[2 * kMaxStack + 1];
     int64_t words[2 * kMaxStack + 1];
@@ -162,6 +176,7 @@ hipError_t launch_kernel(const char *name, void (*k)(A), dim3 grid, dim3 block, 
 hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);
 hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s);
 hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s);
+hipError_t launch_apply(const ApplyArgs &a, int device_cus, hipStream_t s);
 // Searches every level of every pair and writes a.out; a.state and *a.done
 // must be zero.
 hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s);

@@ -1195,6 +1195,68 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
         finalize_level0(a);
 }
 
+// ---------------------------------------------------------------- apply shifts
+
+// One output byte o of a row: pixel o / 3, channel o % 3, from source row sy
+// (already clamped when fill is 1; -1 when the whole row is outside for fill 0).
+__device__ __forceinline__ uint8_t shifted_byte(const ApplyArgs &a, const uint8_t *src, int sy, int64_t o, int dx)
+{
+    const int64_t x = o / 3, c = o - 3 * x;
+    int64_t sx = x - dx;
+    if (sy < 0)
+        return 0;
+    if (sx < 0 || sx >= a.width) {
+        if (a.fill == 0)
+            return 0;
+        sx = sx < 0 ? 0 : a.width - 1;
+    }
+    return src[(int64_t)sy * a.stride + 3 * sx + c];
+}
+
+// Workgroups walk the rows of all images (row r = image r / height, row
+// r % height).  A thread writes 16 output bytes at a time: where those bytes
+// come from 16 consecutive source bytes whose covering aligned dwords lie
+// inside the source row, five aligned dword loads and v_alignbyte realign
+// them; the rest (row ends, shifted-in pixels) goes byte by byte.
+__global__ __launch_bounds__(256) void k_apply(ApplyArgs a)
+{
+    const int64_t rows = (int64_t)a.n * a.height;
+    const int64_t row = 3 * (int64_t)a.width;
+    for (int64_t rr = blockIdx.x; rr < rows; rr += gridDim.x) {
+        const int img = (int)(rr / a.height);
+        const int y = (int)(rr - (int64_t)img * a.height);
+        const int dx = a.shifts[2 * img], dy = a.shifts[2 * img + 1];
+        int sy = y - dy;
+        if (sy < 0 || sy >= a.height)
+            sy = a.fill == 1 ? (sy < 0 ? 0 : a.height - 1) : -1;
+        const uint8_t *src = a.rgb[img];
+        uint8_t *dst = a.out[img] + (int64_t)y * a.out_stride;
+        const int64_t shift = 3 * (int64_t)dx;  // output byte o reads source byte o - shift
+        const uint8_t *srow = sy >= 0 ? src + (int64_t)sy * a.stride : src;
+        for (int64_t o = 16 * (int64_t)threadIdx.x; o < row; o += 16 * (int64_t)blockDim.x) {
+            const int64_t s0 = o - shift;
+            if (a.aligned && sy >= 0 && o + 16 <= row && s0 >= 0 && (s0 & ~3ll) + 20 <= row) {
+                const uint32_t *w = (const uint32_t *)(srow + (s0 & ~3ll));
+                const uint32_t r = (uint32_t)(s0 & 3);
+                uint32_t v[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k)
+                    v[k] = w[k];
+                uint4 q;
+                q.x = __builtin_amdgcn_alignbyte(v[1], v[0], r);
+                q.y = __builtin_amdgcn_alignbyte(v[2], v[1], r);
+                q.z = __builtin_amdgcn_alignbyte(v[3], v[2], r);
+                q.w = __builtin_amdgcn_alignbyte(v[4], v[3], r);
+                *(uint4 *)(dst + o) = q;
+            } else {
+                const int64_t end = o + 16 < row ? o + 16 : row;
+                for (int64_t b = o; b < end; ++b)
+                    dst[b] = shifted_byte(a, src, sy, b, dx);
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -1251,6 +1313,14 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     c.pad_ = 0;
     c.g = a.g;
     return launch_kernel("k_pyramid_coarse", k_pyramid_coarse, dim3(a.n), dim3(256), s, c);
+}
+
+hipError_t launch_apply(const ApplyArgs &a, int cus, hipStream_t s)
+{
+    const int64_t rows = (int64_t)a.n * a.height;
+    const int64_t cap = (int64_t)cus * 64;
+    const int64_t blocks = rows < cap ? rows : cap;
+    return launch_kernel("k_apply", k_apply, dim3((unsigned)blocks), dim3(256), s, a);
 }
 
 hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)

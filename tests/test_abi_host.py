@@ -250,3 +250,19 @@ def test_profile_state_machine(mtb):
     assert L.mtb_profile_pause(1) == 0 and L.mtb_profile_pause(0) == 0
     assert L.mtb_profile_end(out, 4, ctypes.byref(cnt)) == 0 and cnt.value == 0
     assert L.mtb_profile_pause(0) == 1
+
+
+def test_apply_shifts_validation(mtb):
+    L = _c(mtb)
+    n = 2
+    ins = (ctypes.c_void_p * n)(0x1000, 0x2000)
+    outs = (ctypes.c_void_p * n)(0x3000, 0x4000)
+    args = [ins, n, 64, 48, 192, FAKE, 0, outs, 192, NULL]
+    for i, v in ((0, NULL), (1, 0), (1, 33), (2, 0), (3, 0), (4, 191), (5, NULL), (6, 2), (6, -1),
+                 (7, NULL), (8, 191)):
+        bad = list(args)
+        bad[i] = v
+        assert L.mtb_apply_shifts(*bad) == 1, (i, v)
+    bad = list(args)
+    bad[7] = (ctypes.c_void_p * n)(0x3000, 0)
+    assert L.mtb_apply_shifts(*bad) == 1

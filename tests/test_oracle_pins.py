@@ -331,3 +331,44 @@ def test_stack_threads_do_not_change_results():
     a = oracle.align_stack(imgs, 3, threads=1)
     b = oracle.align_stack(imgs, 3, threads=4)
     assert np.array_equal(a["shifts"], b["shifts"]) and np.array_equal(a["errs"], b["errs"])
+
+
+# ---- applying the shift (Section III-B): two fill readings, pinned to an
+# independent translation (the generator's edge-replicate slicing) and to
+# properties of a translation.
+
+def test_apply_shift_edge_fill_equals_independent_translation():
+    rng = np.random.default_rng(17)
+    for H, W in ((1, 1), (1, 9), (7, 1), (13, 17), (40, 33)):
+        img = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+        for dx in (-W - 3, -W, -5, -1, 0, 1, 4, W - 1, W + 2):
+            for dy in (-H - 1, -2, 0, 3, H):
+                assert np.array_equal(oracle.apply_shift(img, dx, dy, 1), synth.translate(img, dx, dy)), (H, W, dx, dy)
+
+
+def test_apply_shift_zero_fill_is_edge_fill_inside_and_zero_outside():
+    rng = np.random.default_rng(18)
+    img = rng.integers(1, 256, (21, 30, 3), dtype=np.uint8)   # no zero bytes in the image
+    for dx, dy in ((0, 0), (3, -2), (-7, 5), (29, 20), (-31, 0), (0, 21)):
+        z = oracle.apply_shift(img, dx, dy, 0)
+        e = oracle.apply_shift(img, dx, dy, 1)
+        ys, xs = np.mgrid[0:21, 0:30]
+        inside = (ys - dy >= 0) & (ys - dy < 21) & (xs - dx >= 0) & (xs - dx < 30)
+        assert np.array_equal(z[inside], e[inside])
+        assert not z[~inside].any()
+        assert int(inside.sum()) == max(0, 21 - abs(dy)) * max(0, 30 - abs(dx))
+
+
+def test_apply_shift_undoes_a_translation_and_ignores_row_padding():
+    rng = np.random.default_rng(19)
+    img = rng.integers(0, 256, (50, 64, 3), dtype=np.uint8)
+    assert np.array_equal(oracle.apply_shift(img, 0, 0, 0), img)
+    tx, ty = 6, -4
+    moved = synth.translate(img, tx, ty)
+    back = oracle.apply_shift(moved, -tx, -ty, 0)
+    # back[y][x] = moved[y + ty][x + tx] = img[y][x] wherever that stays in the image.
+    assert np.array_equal(back[-ty:50, 0:64 - tx], img[-ty:50, 0:64 - tx])
+    assert not back[:-ty].any() and not back[:, 64 - tx:].any()
+    padded = np.zeros((50, 64 + 5, 3), np.uint8)
+    padded[:, :64] = moved
+    assert np.array_equal(oracle.apply_shift(padded[:, :64], -tx, -ty, 1), oracle.apply_shift(moved, -tx, -ty, 1))
