@@ -86,15 +86,16 @@ def load_traffic(kernel):
     return t.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(imgs, levels, ref, mp_total, max_threads, min_seconds):
+def cpu_baseline(imgs, levels, ref, mp_total, max_threads, min_seconds, chained=False):
     """The CPU oracle on whole stack alignments, repeated for at least min_seconds."""
     import oracle
 
+    run = oracle.align_stack_chained if chained else oracle.align_stack
     threads = max(1, min(max_threads, len(imgs), os.cpu_count() or 1))
     reps = 0
     t0 = time.perf_counter()
     while True:
-        out = oracle.align_stack(imgs, levels, ref_index=ref, threads=threads)
+        out = run(imgs, levels, ref_index=ref, threads=threads)
         reps += 1
         dt = time.perf_counter() - t0
         if dt >= min_seconds:
@@ -352,7 +353,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stack7_6000x4000",
-                    choices=["stack7_6000x4000", "pair_4096x3072", "pair_512x384", "batch64_uneven",
+                    choices=["stack7_6000x4000", "stack7_6000x4000_chained", "pair_4096x3072", "pair_512x384",
+                             "batch64_uneven",
                              "served_poisson200", "apply7_6000x4000"])
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
     ap.add_argument("--serve-slots", type=int, default=4, help="served mode: stacks in flight at most")
@@ -394,7 +396,8 @@ def main():
 
     log(f"generating {args.workload} ...")
     t0 = time.perf_counter()
-    w = synth.workload(args.workload)
+    chained = args.workload.endswith("_chained")
+    w = synth.workload(args.workload[:-len("_chained")] if chained else args.workload)
     (imgs, true_shifts, ref), = w.stacks
     L = w.levels
     n = len(imgs)
@@ -407,8 +410,10 @@ def main():
     shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)
     errs = torch.empty(n, dtype=torch.int32, device=dev)
 
+    align = mtb.mtb_align_stack_chained if chained else mtb.mtb_align_stack
+
     def step():
-        mtb.mtb_align_stack(d_imgs, L, ref_index=ref, workspace=ws, shifts=shifts, errs=errs)
+        align(d_imgs, L, ref_index=ref, workspace=ws, shifts=shifts, errs=errs)
 
     for _ in range(args.warmup):
         step()
@@ -494,7 +499,7 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {
-            "workload": w.name,
+            "workload": args.workload,
             "images": n,
             "width": W,
             "height": H,
@@ -512,7 +517,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        want, cpu = cpu_baseline(imgs, L, ref, mp_total, args.cpu_threads, args.cpu_seconds)
+        want, cpu = cpu_baseline(imgs, L, ref, mp_total, args.cpu_threads, args.cpu_seconds, chained)
         result["cpu_baseline"] = cpu
         result["parity_vs_oracle"] = bool(np.array_equal(gpu_shifts, want["shifts"]) and
                                           np.array_equal(gpu_errs, want["errs"]))

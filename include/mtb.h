@@ -184,6 +184,22 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
                            uint32_t *d_trace, void *stream);
 
 /*
+ * Chained stack alignment (Section III-A: consecutive exposures are the ones
+ * compared; Section III-B: a stack of n images takes n - 1 pairwise
+ * alignments).  Image i is aligned against its neighbour towards the
+ * reference (i + 1 below it, i - 1 above), whose exposure is closest to its
+ * own, and the pairwise shifts are summed along the chain, translations
+ * composing by addition.  Arguments and buffers as for mtb_align_stack;
+ * d_shifts receives the summed shift of each image against the reference,
+ * d_errs and d_trace the pairwise level-0 errors and traces.
+ */
+mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
+                                   int32_t height, int64_t row_stride, int32_t levels,
+                                   int32_t exclude_range, int32_t ref_index, void *d_workspace,
+                                   size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                                   uint32_t *d_trace, void *stream);
+
+/*
  * Translates every image of a stack by its shift (Section III-B: the shift
  * found for an exposure is applied to it, bringing it onto the reference):
  *   out_i[y][x] = in_i[y - dy_i][x - dx_i]   (all three channels)

@@ -29,6 +29,7 @@ _lib = None
 
 __all__ = [
     "apply_shift",
+    "align_stack_chained",
     "build",
     "gray",
     "downsample",
@@ -259,6 +260,35 @@ def align_stack(images, levels: int, ref_index: int | None = None, exclude: int 
     if keep:
         out["pyramids"] = pyrs
     return out
+
+
+def align_stack_chained(images, levels: int, ref_index: int | None = None, exclude: int = 4,
+                        threads: int = 1) -> dict:
+    """Chained stack alignment: image k against its neighbour towards the reference
+    (k + 1 below it, k - 1 above), the pairwise shifts summed along the chain
+    (translations compose by addition; Section III-A compares consecutive
+    exposures, Section III-B aligns a stack pairwise).
+
+    Returns ``shifts`` (summed, against the reference), ``errs`` and ``pairs``
+    (pairwise results, keyed by the moving image).
+    """
+    n = len(images)
+    if n < 1:
+        raise ValueError("empty stack")
+    ref = n // 2 if ref_index is None or ref_index < 0 else int(ref_index)
+    if not 0 <= ref < n:
+        raise ValueError("ref_index out of range")
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        pyrs = list(ex.map(lambda im: pyramid(im, levels, exclude), images))
+        others = [k for k in range(n) if k != ref]
+        nb = {k: (k + 1 if k < ref else k - 1) for k in others}
+        res = dict(zip(others, ex.map(lambda k: search(pyrs[nb[k]], pyrs[k]), others)))
+    shifts = np.zeros((n, 2), np.int64)
+    errs = np.zeros(n, np.int64)
+    for k in list(range(ref - 1, -1, -1)) + list(range(ref + 1, n)):
+        shifts[k] = np.array(res[k]["shift"]) + shifts[nb[k]]
+        errs[k] = res[k]["err"]
+    return {"shifts": shifts.astype(np.int32), "errs": errs, "ref_index": ref, "pairs": res}
 
 
 def apply_shift(img: np.ndarray, dx: int, dy: int, fill: int = 0) -> np.ndarray:

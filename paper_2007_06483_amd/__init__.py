@@ -35,6 +35,7 @@ __all__ = [
     "mtb_bitmaps",
     "mtb_align_pair",
     "mtb_align_stack",
+    "mtb_align_stack_chained",
     "mtb_apply_shifts",
     "MTB_FILL_ZERO",
     "MTB_FILL_EDGE",
@@ -151,6 +152,8 @@ def lib():
     L.mtb_align_pair.restype = ctypes.c_int
     L.mtb_align_stack.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, i32, i32, P, sz, P, P, P, P]
     L.mtb_align_stack.restype = ctypes.c_int
+    L.mtb_align_stack_chained.argtypes = L.mtb_align_stack.argtypes
+    L.mtb_align_stack_chained.restype = ctypes.c_int
     L.mtb_apply_shifts.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, P, i32, ctypes.POINTER(P), i64, P]
     L.mtb_apply_shifts.restype = ctypes.c_int
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
@@ -284,9 +287,20 @@ def mtb_align_pair(bm_ref: torch.Tensor, bm_mov: torch.Tensor, width: int, heigh
     return {"shift": shift, "err": err, "trace": tr, "level_shifts": ls}
 
 
+def mtb_align_stack_chained(images, levels: int, exclude_range: int = 4, ref_index: int = -1,
+                            workspace: torch.Tensor | None = None, trace: bool = False, shifts=None,
+                            errs=None, stream=None) -> dict:
+    """Chained stack: each image against its neighbour towards the reference, shifts summed.
+
+    Same arguments and results as mtb_align_stack; ``errs`` and ``trace`` are pairwise.
+    """
+    return mtb_align_stack(images, levels, exclude_range, ref_index, workspace, trace, shifts, errs,
+                           stream, _entry="mtb_align_stack_chained")
+
+
 def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int = -1,
                     workspace: torch.Tensor | None = None, trace: bool = False, shifts=None,
-                    errs=None, stream=None) -> dict:
+                    errs=None, stream=None, _entry: str = "mtb_align_stack") -> dict:
     """Align every (H, W, 3) image of a stack against the reference (n // 2 by default).
 
     Returns device tensors ``shifts`` int32[n][2], ``errs`` int32[n] (the uint32
@@ -308,10 +322,10 @@ def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int 
         errs = torch.empty(n, dtype=torch.int32, device=dev)
     tr = torch.empty((n, levels, 9), dtype=torch.int32, device=dev) if trace else None
     ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in images])
-    _check("mtb_align_stack",
-           lib().mtb_align_stack(ptrs, n, W, H, stride, levels, exclude_range, ref_index,
-                                 _ptr(workspace), workspace.numel(), _ptr(shifts), _ptr(errs),
-                                 _ptr(tr), _stream(stream)))
+    _check(_entry,
+           getattr(lib(), _entry)(ptrs, n, W, H, stride, levels, exclude_range, ref_index,
+                                  _ptr(workspace), workspace.numel(), _ptr(shifts), _ptr(errs),
+                                  _ptr(tr), _stream(stream)))
     return {"shifts": shifts, "errs": errs, "trace": tr, "workspace": workspace}
 
 

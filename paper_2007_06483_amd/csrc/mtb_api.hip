@@ -426,11 +426,16 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
     return device_status(launch_search(a, cus, s));
 }
 
-mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
-                           int32_t height, int64_t row_stride, int32_t levels,
-                           int32_t exclude_range, int32_t ref_index, void *d_workspace,
-                           size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
-                           uint32_t *d_trace, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Both stack modes: every image against the reference, or (chained) every
+// image against its neighbour towards the reference, the shifts then summed.
+mtb_status align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
+                       int64_t row_stride, int32_t levels, int32_t exclude_range, int32_t ref_index,
+                       void *d_workspace, size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                       uint32_t *d_trace, bool chained, hipStream_t s)
 {
     Geometry g;
     if (!h_d_rgb || n < 1 || n > kMaxStack || !d_workspace || !d_shifts || !d_errs ||
@@ -453,13 +458,12 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
     const int cus = current_device_cus();
     if (cus <= 0)
         return MTB_ERR_UNSUPPORTED;
-    hipStream_t s = (hipStream_t)stream;
 
     PairSet ps;
     for (int i = 0; i < n; ++i) {
         ps.rgb[i] = h_d_rgb[i];
         if (i != ref) {
-            ps.ref_img[ps.npairs] = ref;
+            ps.ref_img[ps.npairs] = chained ? (i < ref ? i + 1 : i - 1) : ref;
             ps.mov_img[ps.npairs] = i;
             ps.out_row[ps.npairs++] = i;
         }
@@ -483,7 +487,34 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
         z.words[z.count++] = 9 * (int64_t)levels * n;
     }
     uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
-    return device_status(enqueue_set(ps, g, row_stride, align, exclude_range, ws, out, z, cus, s));
+    hipError_t e = enqueue_set(ps, g, row_stride, align, exclude_range, ws, out, z, cus, s);
+    if (e == hipSuccess && chained && n > 1)
+        e = launch_chain(d_shifts, n, ref, s);
+    return device_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
+                           int32_t height, int64_t row_stride, int32_t levels,
+                           int32_t exclude_range, int32_t ref_index, void *d_workspace,
+                           size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                           uint32_t *d_trace, void *stream)
+{
+    return align_stack(h_d_rgb, n, width, height, row_stride, levels, exclude_range, ref_index, d_workspace,
+                       workspace_bytes, d_shifts, d_errs, d_trace, false, (hipStream_t)stream);
+}
+
+mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
+                                   int32_t height, int64_t row_stride, int32_t levels,
+                                   int32_t exclude_range, int32_t ref_index, void *d_workspace,
+                                   size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                                   uint32_t *d_trace, void *stream)
+{
+    return align_stack(h_d_rgb, n, width, height, row_stride, levels, exclude_range, ref_index, d_workspace,
+                       workspace_bytes, d_shifts, d_errs, d_trace, true, (hipStream_t)stream);
 }
 
 mtb_status mtb_apply_shifts(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,

@@ -177,6 +177,9 @@ hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);
 hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s);
 hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s);
 hipError_t launch_apply(const ApplyArgs &a, int device_cus, hipStream_t s);
+// Turns the pairwise shifts of a chained stack (image i against its neighbour
+// towards ref) into shifts against ref, in place.
+hipError_t launch_chain(int32_t *d_shifts, int n, int ref, hipStream_t s);
 // Searches every level of every pair and writes a.out; a.state and *a.done
 // must be zero.
 hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s);

@@ -1257,6 +1257,33 @@ __global__ __launch_bounds__(256) void k_apply(ApplyArgs a)
     }
 }
 
+// ---------------------------------------------------------------- chained stacks
+
+// Translations compose by addition: the shift of image i against the
+// reference is its shift against its neighbour towards the reference plus
+// that neighbour's shift against the reference.  One lane walks each side.
+struct ChainArgs {
+    int32_t *shifts;
+    int32_t n, ref;
+};
+
+__global__ void k_chain(ChainArgs a)
+{
+    int32_t *shifts = a.shifts;
+    const int n = a.n, ref = a.ref;
+    if (threadIdx.x == 0) {
+        for (int i = ref - 2; i >= 0; --i) {
+            shifts[2 * i] += shifts[2 * (i + 1)];
+            shifts[2 * i + 1] += shifts[2 * (i + 1) + 1];
+        }
+    } else if (threadIdx.x == 1) {
+        for (int i = ref + 2; i < n; ++i) {
+            shifts[2 * i] += shifts[2 * (i - 1)];
+            shifts[2 * i + 1] += shifts[2 * (i - 1) + 1];
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -1313,6 +1340,11 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
     c.pad_ = 0;
     c.g = a.g;
     return launch_kernel("k_pyramid_coarse", k_pyramid_coarse, dim3(a.n), dim3(256), s, c);
+}
+
+hipError_t launch_chain(int32_t *d_shifts, int n, int ref, hipStream_t s)
+{
+    return launch_kernel("k_chain", k_chain, dim3(1), dim3(64), s, ChainArgs{d_shifts, n, ref});
 }
 
 hipError_t launch_apply(const ApplyArgs &a, int cus, hipStream_t s)

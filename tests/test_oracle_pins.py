@@ -372,3 +372,29 @@ def test_apply_shift_undoes_a_translation_and_ignores_row_padding():
     padded = np.zeros((50, 64 + 5, 3), np.uint8)
     padded[:, :64] = moved
     assert np.array_equal(oracle.apply_shift(padded[:, :64], -tx, -ty, 1), oracle.apply_shift(moved, -tx, -ty, 1))
+
+
+# ---- chained stacks: pairwise along the exposure order, shifts summed.
+
+def test_chained_two_images_is_the_pair():
+    ref, mov, _ = synth.make_rect_pair(160, 120, 12, 31, 6)
+    ch = oracle.align_stack_chained([ref, mov], 4, ref_index=0)
+    direct = oracle.align_pair(ref, mov, 4)
+    assert tuple(ch["shifts"][1]) == direct["shift"] and ch["errs"][1] == direct["err"]
+
+
+def test_chained_sums_planted_translations():
+    # One exposure of a sharp scene, each image translated by its own planted
+    # shift: neighbours differ by t_k - t_{k+1}, and the summed chain must give
+    # every image's shift against the reference, -(t_k - t_ref).
+    rng = np.random.default_rng(32)
+    rad = synth.rect_field(240, 180, 30, rng)
+    base = synth.expose(rad, 0.0)
+    planted = [(5, -3), (-2, 4), (0, 0), (6, 1), (-4, -6)]
+    imgs = [synth.translate(base, tx, ty) for tx, ty in planted]
+    ch = oracle.align_stack_chained(imgs, 5, ref_index=2)
+    direct = oracle.align_stack(imgs, 5, ref_index=2)
+    want = np.array([(-(tx - 0), -(ty - 0)) for tx, ty in planted], np.int32)
+    assert np.array_equal(direct["shifts"], want)
+    assert np.array_equal(ch["shifts"], want)
+    assert ch["errs"][2] == 0 and tuple(ch["shifts"][2]) == (0, 0)
