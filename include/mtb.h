@@ -259,6 +259,31 @@ mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32
                            uint32_t *d_errs, void *stream);
 
 /*
+ * Quadrant check for rotation (Section II: to find out whether a pair needs
+ * rotational alignment, the image is split into quadrants and each quadrant is
+ * aligned on its own).  The reference and moving images are cut into four
+ * quadrants, q = 0 top-left, 1 top-right, 2 bottom-left, 3 bottom-right,
+ * split at column width / 2 and row height / 2, and each quadrant pair is
+ * aligned as mtb_align_pair would align it (its own pyramids, medians and
+ * bitmaps).  A rotation is flagged when two quadrants' shifts differ by more
+ * than `tolerance` pixels along either axis (the paper gives no threshold).
+ *   d_ref_rgb, d_mov_rgb  device RGB images (same size and stride)
+ *   levels               1 .. mtb_max_levels(width / 2, height / 2)
+ *   d_workspace          >= mtb_quadrant_workspace_bytes(width, height, row_stride, levels)
+ *   d_shifts             int32[4][2] receives each quadrant's (dx, dy)
+ *   d_errs               uint32[4] receives each quadrant's level-0 error
+ *   d_flag               int32[1] receives 1 if a rotation is flagged, else 0
+ * Errors: MTB_ERR_INVALID_ARG (pointers, sizes, stride, levels, tolerance < 0),
+ *         MTB_ERR_WORKSPACE, MTB_ERR_DEVICE.
+ */
+size_t mtb_quadrant_workspace_bytes(int32_t width, int32_t height, int64_t row_stride, int32_t levels);
+mtb_status mtb_align_quadrants(const uint8_t *d_ref_rgb, const uint8_t *d_mov_rgb, int32_t width,
+                               int32_t height, int64_t row_stride, int32_t levels,
+                               int32_t exclude_range, int32_t tolerance, void *d_workspace,
+                               size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                               int32_t *d_flag, void *stream);
+
+/*
  * Per-kernel timing for benchmarks.  Between mtb_profile_begin and
  * mtb_profile_end, every kernel that library calls made from the calling
  * thread launch is bracketed by two HIP events recorded on its stream; with

@@ -28,6 +28,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 __all__ = [
+    "quadrants",
+    "align_quadrants",
     "apply_shift",
     "align_stack_chained",
     "build",
@@ -298,3 +300,25 @@ def apply_shift(img: np.ndarray, dx: int, dy: int, fill: int = 0) -> np.ndarray:
     out = np.empty((H, W, 3), np.uint8)
     _load().oracle_apply_shift(_ptr(a), W, H, s, int(dx), int(dy), int(fill), _ptr(out), 3 * W)
     return out
+
+
+def quadrants(img: np.ndarray):
+    """The four quadrants (top-left, top-right, bottom-left, bottom-right) of an
+    (H, W, 3) image, split at column W // 2 and row H // 2."""
+    a = np.asarray(img)
+    H, W = a.shape[:2]
+    w0, h0 = W // 2, H // 2
+    return [a[:h0, :w0], a[:h0, w0:], a[h0:, :w0], a[h0:, w0:]]
+
+
+def align_quadrants(ref_img: np.ndarray, mov_img: np.ndarray, levels: int, exclude: int = 4,
+                    tolerance: int = 1) -> dict:
+    """Align each quadrant pair on its own (Section II, after Ward: quadrants that
+    disagree reveal a rotation).  The flag is raised when two quadrants' shifts
+    differ by more than `tolerance` along either axis."""
+    res = [align_pair(np.ascontiguousarray(r), np.ascontiguousarray(m), levels, exclude)
+           for r, m in zip(quadrants(ref_img), quadrants(mov_img))]
+    shifts = np.array([r["shift"] for r in res], np.int32)
+    errs = np.array([r["err"] for r in res], np.int64)
+    spread = (shifts.max(axis=0) - shifts.min(axis=0)).max()
+    return {"shifts": shifts, "errs": errs, "flag": int(spread > tolerance)}

@@ -37,6 +37,8 @@ __all__ = [
     "mtb_align_stack",
     "mtb_align_stack_chained",
     "mtb_apply_shifts",
+    "mtb_quadrant_workspace_bytes",
+    "mtb_align_quadrants",
     "MTB_FILL_ZERO",
     "MTB_FILL_EDGE",
     "mtb_batch_workspace_bytes",
@@ -154,6 +156,10 @@ def lib():
     L.mtb_align_stack.restype = ctypes.c_int
     L.mtb_align_stack_chained.argtypes = L.mtb_align_stack.argtypes
     L.mtb_align_stack_chained.restype = ctypes.c_int
+    L.mtb_quadrant_workspace_bytes.argtypes = [i32, i32, i64, i32]
+    L.mtb_quadrant_workspace_bytes.restype = sz
+    L.mtb_align_quadrants.argtypes = [P, P, i32, i32, i64, i32, i32, i32, P, sz, P, P, P, P]
+    L.mtb_align_quadrants.restype = ctypes.c_int
     L.mtb_apply_shifts.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, P, i32, ctypes.POINTER(P), i64, P]
     L.mtb_apply_shifts.restype = ctypes.c_int
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
@@ -359,6 +365,32 @@ def mtb_apply_shifts(images, shifts: torch.Tensor, fill: int = MTB_FILL_ZERO, ou
            lib().mtb_apply_shifts(ins, n, W, H, stride, _ptr(shifts), int(fill), outs, ostride,
                                   _stream(stream)))
     return out
+
+
+def mtb_quadrant_workspace_bytes(width: int, height: int, row_stride: int, levels: int) -> int:
+    return int(lib().mtb_quadrant_workspace_bytes(width, height, row_stride, levels))
+
+
+def mtb_align_quadrants(ref: torch.Tensor, mov: torch.Tensor, levels: int, exclude_range: int = 4,
+                        tolerance: int = 1, workspace: torch.Tensor | None = None, stream=None) -> dict:
+    """Align the four quadrant pairs of (ref, mov); flag a suspected rotation.
+
+    Returns device tensors ``shifts`` int32[4][2], ``errs`` int32[4], ``flag`` int32[1].
+    """
+    W, H, stride = _rgb_geometry(ref)
+    if _rgb_geometry(mov) != (W, H, stride):
+        raise ValueError("both images must share size and stride")
+    dev = ref.device
+    need = mtb_quadrant_workspace_bytes(W, H, stride, levels)
+    workspace = _buffer(max(need, 1), dev, workspace)
+    shifts = torch.empty((4, 2), dtype=torch.int32, device=dev)
+    errs = torch.empty(4, dtype=torch.int32, device=dev)
+    flag = torch.empty(1, dtype=torch.int32, device=dev)
+    _check("mtb_align_quadrants",
+           lib().mtb_align_quadrants(_ptr(ref), _ptr(mov), W, H, stride, levels, exclude_range, tolerance,
+                                     _ptr(workspace), workspace.numel(), _ptr(shifts), _ptr(errs),
+                                     _ptr(flag), _stream(stream)))
+    return {"shifts": shifts, "errs": errs, "flag": flag}
 
 
 def _batch_items(pairs):

@@ -239,6 +239,25 @@ bool batch_item_valid(const mtb_batch_item &it, Geometry *g)
            it.row_stride >= 3 * (int64_t)it.width;
 }
 
+// The four quadrant pairs of a reference / moving pair as batch items
+// (q = 0 top-left, 1 top-right, 2 bottom-left, 3 bottom-right).
+void quadrant_items(const uint8_t *ref, const uint8_t *mov, int32_t W, int32_t H, int64_t stride,
+                    int32_t levels, mtb_batch_item *it)
+{
+    const int32_t w0 = W / 2, h0 = H / 2;
+    for (int q = 0; q < 4; ++q) {
+        const int32_t x = (q & 1) ? w0 : 0, y = (q & 2) ? h0 : 0;
+        const int64_t off = (int64_t)y * stride + 3 * (int64_t)x;
+        it[q].d_ref_rgb = ref ? ref + off : nullptr;
+        it[q].d_mov_rgb = mov ? mov + off : nullptr;
+        it[q].row_stride = stride;
+        it[q].width = (q & 1) ? W - w0 : w0;
+        it[q].height = (q & 2) ? H - h0 : h0;
+        it[q].levels = levels;
+        it[q].reserved = 0;
+    }
+}
+
 }  // namespace
 }  // namespace mtb
 
@@ -616,6 +635,39 @@ mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32
             return MTB_ERR_DEVICE;
     }
     return MTB_OK;
+}
+
+size_t mtb_quadrant_workspace_bytes(int32_t width, int32_t height, int64_t row_stride, int32_t levels)
+{
+    if (width < 2 || height < 2 || row_stride < 3 * (int64_t)width)
+        return 0;
+    mtb_batch_item it[4];
+    const uint8_t *fake = (const uint8_t *)(uintptr_t)kAlign;  // sizes only; never dereferenced
+    quadrant_items(fake, fake, width, height, row_stride, levels, it);
+    return mtb_batch_workspace_bytes(it, 4);
+}
+
+mtb_status mtb_align_quadrants(const uint8_t *d_ref_rgb, const uint8_t *d_mov_rgb, int32_t width,
+                               int32_t height, int64_t row_stride, int32_t levels,
+                               int32_t exclude_range, int32_t tolerance, void *d_workspace,
+                               size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                               int32_t *d_flag, void *stream)
+{
+    if (!d_ref_rgb || !d_mov_rgb || !d_flag || tolerance < 0 || width < 2 || height < 2 ||
+        row_stride < 3 * (int64_t)width)
+        return MTB_ERR_INVALID_ARG;
+    mtb_batch_item it[4];
+    quadrant_items(d_ref_rgb, d_mov_rgb, width, height, row_stride, levels, it);
+    const size_t need = mtb_batch_workspace_bytes(it, 4);
+    if (need == 0)
+        return MTB_ERR_INVALID_ARG;
+    if (workspace_bytes < need)
+        return MTB_ERR_WORKSPACE;
+    const mtb_status st = mtb_align_batch(it, 4, exclude_range, d_workspace, workspace_bytes, d_shifts,
+                                          d_errs, stream);
+    if (st != MTB_OK)
+        return st;
+    return device_status(launch_quadrant_flag(d_shifts, tolerance, d_flag, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -180,6 +180,8 @@ hipError_t launch_apply(const ApplyArgs &a, int device_cus, hipStream_t s);
 // Turns the pairwise shifts of a chained stack (image i against its neighbour
 // towards ref) into shifts against ref, in place.
 hipError_t launch_chain(int32_t *d_shifts, int n, int ref, hipStream_t s);
+// d_flag[0] = 1 if two of the four shifts differ by more than tol along an axis.
+hipError_t launch_quadrant_flag(const int32_t *d_shifts, int32_t tol, int32_t *d_flag, hipStream_t s);
 // Searches every level of every pair and writes a.out; a.state and *a.done
 // must be zero.
 hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s);

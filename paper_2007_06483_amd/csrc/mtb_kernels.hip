@@ -1284,6 +1284,29 @@ __global__ void k_chain(ChainArgs a)
     }
 }
 
+// ---------------------------------------------------------------- quadrant check
+
+struct QuadFlagArgs {
+    const int32_t *shifts;  // [4][2]
+    int32_t *flag;
+    int32_t tol, pad_;
+};
+
+__global__ void k_quadrant_flag(QuadFlagArgs a)
+{
+    if (threadIdx.x != 0)
+        return;
+    int32_t f = 0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j)
+            for (int c = 0; c < 2; ++c) {
+                const int32_t d = a.shifts[2 * i + c] - a.shifts[2 * j + c];
+                if (d > a.tol || -d > a.tol)
+                    f = 1;
+            }
+    a.flag[0] = f;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -1345,6 +1368,12 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
 hipError_t launch_chain(int32_t *d_shifts, int n, int ref, hipStream_t s)
 {
     return launch_kernel("k_chain", k_chain, dim3(1), dim3(64), s, ChainArgs{d_shifts, n, ref});
+}
+
+hipError_t launch_quadrant_flag(const int32_t *d_shifts, int32_t tol, int32_t *d_flag, hipStream_t s)
+{
+    return launch_kernel("k_quadrant_flag", k_quadrant_flag, dim3(1), dim3(64), s,
+                         QuadFlagArgs{d_shifts, d_flag, tol, 0});
 }
 
 hipError_t launch_apply(const ApplyArgs &a, int cus, hipStream_t s)

@@ -266,3 +266,21 @@ def test_apply_shifts_validation(mtb):
     bad = list(args)
     bad[7] = (ctypes.c_void_p * n)(0x3000, 0)
     assert L.mtb_apply_shifts(*bad) == 1
+
+
+def test_quadrant_validation(mtb):
+    L = _c(mtb)
+    ws = L.mtb_quadrant_workspace_bytes(64, 48, 192, 3)
+    assert ws > 0
+    assert L.mtb_quadrant_workspace_bytes(64, 48, 192, 6) == 0   # too many levels for 32x24 quadrants
+    assert L.mtb_quadrant_workspace_bytes(1, 48, 192, 1) == 0
+    assert L.mtb_quadrant_workspace_bytes(64, 48, 191, 3) == 0
+    args = [FAKE, FAKE, 64, 48, 192, 3, 4, 1, FAKE, ws, FAKE, FAKE, FAKE, NULL]
+    for i, v in ((0, NULL), (1, NULL), (2, 1), (3, 1), (4, 100), (5, 6), (6, 256), (7, -1), (8, NULL),
+                 (10, NULL), (11, NULL), (12, NULL)):
+        bad = list(args)
+        bad[i] = v
+        assert L.mtb_align_quadrants(*bad) == 1, (i, v)
+    bad = list(args)
+    bad[9] = ws - 1
+    assert L.mtb_align_quadrants(*bad) == 2

@@ -398,3 +398,39 @@ def test_chained_sums_planted_translations():
     assert np.array_equal(direct["shifts"], want)
     assert np.array_equal(ch["shifts"], want)
     assert ch["errs"][2] == 0 and tuple(ch["shifts"][2]) == (0, 0)
+
+
+# ---- quadrant check (Section II): quadrants agree under a translation and
+# disagree under a rotation.
+
+def _rotate_nearest(img, degrees):
+    """Nearest-neighbour rotation about the image centre (edge pixels repeated)."""
+    H, W = img.shape[:2]
+    t = np.deg2rad(degrees)
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    cy, cx = (H - 1) / 2.0, (W - 1) / 2.0
+    sx = np.cos(t) * (xs - cx) + np.sin(t) * (ys - cy) + cx
+    sy = -np.sin(t) * (xs - cx) + np.cos(t) * (ys - cy) + cy
+    sx = np.clip(np.rint(sx), 0, W - 1).astype(np.int64)
+    sy = np.clip(np.rint(sy), 0, H - 1).astype(np.int64)
+    return img[sy, sx]
+
+
+def test_quadrants_split_and_agree_under_translation():
+    q = oracle.quadrants(np.zeros((7, 9, 3), np.uint8))
+    assert [a.shape[:2] for a in q] == [(3, 4), (3, 5), (4, 4), (4, 5)]
+    rng = np.random.default_rng(41)
+    base = synth.expose(synth.rect_field(480, 360, 60, rng), 0.0)
+    moved = synth.translate(base, 5, -3)
+    r = oracle.align_quadrants(base, moved, 5)
+    assert (r["shifts"] == np.array([-5, 3])).all() and r["flag"] == 0
+
+
+def test_quadrants_flag_a_rotation():
+    rng = np.random.default_rng(42)
+    base = synth.expose(synth.rect_field(480, 360, 60, rng), 0.0)
+    rot = _rotate_nearest(base, 3.0)
+    r = oracle.align_quadrants(base, rot, 5)
+    # A rotation about the centre moves the quadrants in different directions.
+    assert r["flag"] == 1
+    assert len({tuple(s) for s in r["shifts"]}) > 1
