@@ -353,7 +353,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stack7_6000x4000",
-                    choices=["stack7_6000x4000", "stack7_6000x4000_chained", "pair_4096x3072", "pair_512x384",
+                    choices=["stack7_6000x4000", "stack7_6000x4000_chained", "stack7_6000x4000_bytemaps",
+                             "pair_4096x3072", "pair_512x384",
                              "batch64_uneven",
                              "served_poisson200", "apply7_6000x4000"])
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
@@ -397,7 +398,8 @@ def main():
     log(f"generating {args.workload} ...")
     t0 = time.perf_counter()
     chained = args.workload.endswith("_chained")
-    w = synth.workload(args.workload[:-len("_chained")] if chained else args.workload)
+    bytemaps = args.workload.endswith("_bytemaps")
+    w = synth.workload(args.workload.rsplit("_", 1)[0] if (chained or bytemaps) else args.workload)
     (imgs, true_shifts, ref), = w.stacks
     L = w.levels
     n = len(imgs)
@@ -406,11 +408,13 @@ def main():
     W, H = w.width, w.height
     mp_total = n * W * H / 1e6
     lay = mtb.mtb_get_layout(W, H, L)
-    ws = torch.empty(mtb.mtb_stack_workspace_bytes(n, W, H, L), dtype=torch.uint8, device=dev)
+    wsq = mtb.mtb_stack_bytemaps_workspace_bytes if bytemaps else mtb.mtb_stack_workspace_bytes
+    ws = torch.empty(wsq(n, W, H, L), dtype=torch.uint8, device=dev)
     shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)
     errs = torch.empty(n, dtype=torch.int32, device=dev)
 
-    align = mtb.mtb_align_stack_chained if chained else mtb.mtb_align_stack
+    align = (mtb.mtb_align_stack_chained if chained else
+             mtb.mtb_align_stack_bytemaps if bytemaps else mtb.mtb_align_stack)
 
     def step():
         align(d_imgs, L, ref_index=ref, workspace=ws, shifts=shifts, errs=errs)

@@ -184,6 +184,21 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
                            uint32_t *d_trace, void *stream);
 
 /*
+ * The paper's representation, for comparison (Section III-B: T and E kept as
+ * one byte per pixel, 255 or 0, instead of bit-packed words).  Same results
+ * as mtb_align_stack — the error counts do not depend on the representation —
+ * through a byte-map pass and a byte-map search over every level (no
+ * exhaustive coarse windows).  Arguments as for mtb_align_stack, with a
+ * workspace of mtb_stack_bytemaps_workspace_bytes(n, width, height, levels).
+ */
+size_t mtb_stack_bytemaps_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t levels);
+mtb_status mtb_align_stack_bytemaps(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
+                                    int32_t height, int64_t row_stride, int32_t levels,
+                                    int32_t exclude_range, int32_t ref_index, void *d_workspace,
+                                    size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                                    uint32_t *d_trace, void *stream);
+
+/*
  * Chained stack alignment (Section III-A: consecutive exposures are the ones
  * compared; Section III-B: a stack of n images takes n - 1 pairwise
  * alignments).  Image i is aligned against its neighbour towards the

@@ -36,6 +36,8 @@ __all__ = [
     "mtb_align_pair",
     "mtb_align_stack",
     "mtb_align_stack_chained",
+    "mtb_align_stack_bytemaps",
+    "mtb_stack_bytemaps_workspace_bytes",
     "mtb_apply_shifts",
     "mtb_quadrant_workspace_bytes",
     "mtb_align_quadrants",
@@ -156,6 +158,10 @@ def lib():
     L.mtb_align_stack.restype = ctypes.c_int
     L.mtb_align_stack_chained.argtypes = L.mtb_align_stack.argtypes
     L.mtb_align_stack_chained.restype = ctypes.c_int
+    L.mtb_align_stack_bytemaps.argtypes = L.mtb_align_stack.argtypes
+    L.mtb_align_stack_bytemaps.restype = ctypes.c_int
+    L.mtb_stack_bytemaps_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.mtb_stack_bytemaps_workspace_bytes.restype = sz
     L.mtb_quadrant_workspace_bytes.argtypes = [i32, i32, i64, i32]
     L.mtb_quadrant_workspace_bytes.restype = sz
     L.mtb_align_quadrants.argtypes = [P, P, i32, i32, i64, i32, i32, i32, P, sz, P, P, P, P]
@@ -304,6 +310,18 @@ def mtb_align_stack_chained(images, levels: int, exclude_range: int = 4, ref_ind
                            stream, _entry="mtb_align_stack_chained")
 
 
+def mtb_stack_bytemaps_workspace_bytes(n: int, width: int, height: int, levels: int) -> int:
+    return int(lib().mtb_stack_bytemaps_workspace_bytes(n, width, height, levels))
+
+
+def mtb_align_stack_bytemaps(images, levels: int, exclude_range: int = 4, ref_index: int = -1,
+                             workspace: torch.Tensor | None = None, trace: bool = False, shifts=None,
+                             errs=None, stream=None) -> dict:
+    """The stack through byte maps (255/0 per pixel), the paper's representation; same results."""
+    return mtb_align_stack(images, levels, exclude_range, ref_index, workspace, trace, shifts, errs,
+                           stream, _entry="mtb_align_stack_bytemaps")
+
+
 def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int = -1,
                     workspace: torch.Tensor | None = None, trace: bool = False, shifts=None,
                     errs=None, stream=None, _entry: str = "mtb_align_stack") -> dict:
@@ -320,7 +338,8 @@ def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int 
         if _rgb_geometry(im) != (W, H, stride) or im.device != images[0].device:
             raise ValueError("all images of a stack must share size, stride and device")
     dev = images[0].device
-    need = mtb_stack_workspace_bytes(n, W, H, levels)
+    need = (mtb_stack_bytemaps_workspace_bytes if _entry == "mtb_align_stack_bytemaps"
+            else mtb_stack_workspace_bytes)(n, W, H, levels)
     workspace = _buffer(max(need, 1), dev, workspace)
     if shifts is None:
         shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)

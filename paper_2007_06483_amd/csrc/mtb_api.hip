@@ -59,6 +59,19 @@ bool make_geometry(int32_t W, int32_t H, int32_t L, Geometry *g)
     g->med_off = off;
     off = align_up(off + (int64_t)L * 4, kAlign);
     g->bitmaps_bytes = off;
+    // Byte maps (the paper's 255/0 representation, for comparison): the same
+    // guard, a T and an E plane of gray_pitch-byte rows per level, medians.
+    off = kAlign;
+    for (int l = 0; l < L; ++l) {
+        LevelGeom &lv = g->lv[l];
+        const int64_t plane = lv.gray_pitch * lv.h;
+        lv.bt_off = off;
+        off = align_up(off + plane, kAlign);
+        lv.be_off = off;
+        off = align_up(off + plane, kAlign);
+    }
+    g->bmed_off = off;
+    g->bytemaps_bytes = align_up(off + (int64_t)L * 4, kAlign);
     return true;
 }
 
@@ -125,21 +138,23 @@ struct PairSet {
 
 // Workspace bytes of a launch set (from a 256-byte aligned start): pyramids,
 // bitmaps, each pair's search state, ticket counters.
-int64_t set_workspace_bytes(const Geometry &g, int n, int npairs)
+int64_t set_workspace_bytes(const Geometry &g, int n, int npairs, bool bytemaps = false)
 {
-    return n * (g.pyramid_bytes + g.bitmaps_bytes) + npairs * state_stride_words(g.L) * 4 +
-           align_up(4 * kTicketWords, kAlign);
+    return n * (g.pyramid_bytes + (bytemaps ? g.bytemaps_bytes : g.bitmaps_bytes)) +
+           npairs * state_stride_words(g.L) * 4 + align_up(4 * kTicketWords, kAlign);
 }
 
 // Enqueues a launch set on s.  `ws` is 256-byte aligned; `zero` lists output
 // regions to clear first (taken by value, its free slots are used here).
 hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int align, int exclude,
-                       uint8_t *ws, SearchOutputs out, ZeroArgs zero, int cus, hipStream_t s)
+                       uint8_t *ws, SearchOutputs out, ZeroArgs zero, int cus, hipStream_t s,
+                       bool bytemaps = false)
 {
     const int n = ps.n, npairs = ps.npairs;
+    const int64_t mb = bytemaps ? g.bytemaps_bytes : g.bitmaps_bytes;  // maps buffer per image
     uint8_t *pyr0 = ws;
     uint8_t *bm0 = pyr0 + n * g.pyramid_bytes;
-    uint32_t *state = (uint32_t *)(bm0 + n * g.bitmaps_bytes);
+    uint32_t *state = (uint32_t *)(bm0 + n * mb);
     const int64_t sstride = state_stride_words(g.L);
 
     for (int i = 0; i < n; ++i) {
@@ -170,21 +185,21 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     memset(&ba, 0, sizeof(ba));
     for (int i = 0; i < n; ++i) {
         ba.pyr[i] = pyr0 + i * g.pyramid_bytes;
-        ba.bm[i] = bm0 + i * g.bitmaps_bytes;
+        ba.bm[i] = bm0 + i * mb;
     }
     ba.n = n;
     ba.exclude = exclude;
     ba.g = g;
     fill_chunk_starts(g, ba.chunk_start);
-    e = launch_bitmaps(ba, cus, s);
+    e = bytemaps ? launch_bytemaps(ba, cus, s) : launch_bitmaps(ba, cus, s);
     if (e != hipSuccess || npairs == 0)
         return e;
 
     SearchArgs sa;
     memset(&sa, 0, sizeof(sa));
     for (int p = 0; p < npairs; ++p) {
-        sa.ref[p] = bm0 + ps.ref_img[p] * g.bitmaps_bytes;
-        sa.mov[p] = bm0 + ps.mov_img[p] * g.bitmaps_bytes;
+        sa.ref[p] = bm0 + ps.ref_img[p] * mb;
+        sa.mov[p] = bm0 + ps.mov_img[p] * mb;
         out.pair_image[p] = ps.out_row[p];
     }
     sa.state = state;
@@ -193,7 +208,7 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     sa.npairs = npairs;
     sa.out = out;
     sa.g = g;
-    return launch_search(sa, cus, s);
+    return bytemaps ? launch_search_bytes(sa, cus, s) : launch_search(sa, cus, s);
 }
 
 // Items of a batch that share one launch set: same geometry and stride, at
@@ -454,7 +469,7 @@ namespace {
 mtb_status align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
                        int64_t row_stride, int32_t levels, int32_t exclude_range, int32_t ref_index,
                        void *d_workspace, size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
-                       uint32_t *d_trace, bool chained, hipStream_t s)
+                       uint32_t *d_trace, bool chained, hipStream_t s, bool bytemaps = false)
 {
     Geometry g;
     if (!h_d_rgb || n < 1 || n > kMaxStack || !d_workspace || !d_shifts || !d_errs ||
@@ -472,7 +487,9 @@ mtb_status align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, 
         const int ai = row_alignment(h_d_rgb[i], row_stride);
         align = ai < align ? ai : align;
     }
-    if (workspace_bytes < mtb_stack_workspace_bytes(n, width, height, levels))
+    const size_t need = bytemaps ? mtb_stack_bytemaps_workspace_bytes(n, width, height, levels)
+                                 : mtb_stack_workspace_bytes(n, width, height, levels);
+    if (workspace_bytes < need)
         return MTB_ERR_WORKSPACE;
     const int cus = current_device_cus();
     if (cus <= 0)
@@ -506,7 +523,7 @@ mtb_status align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, 
         z.words[z.count++] = 9 * (int64_t)levels * n;
     }
     uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
-    hipError_t e = enqueue_set(ps, g, row_stride, align, exclude_range, ws, out, z, cus, s);
+    hipError_t e = enqueue_set(ps, g, row_stride, align, exclude_range, ws, out, z, cus, s, bytemaps);
     if (e == hipSuccess && chained && n > 1)
         e = launch_chain(d_shifts, n, ref, s);
     return device_status(e);
@@ -524,6 +541,24 @@ mtb_status mtb_align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t wid
 {
     return align_stack(h_d_rgb, n, width, height, row_stride, levels, exclude_range, ref_index, d_workspace,
                        workspace_bytes, d_shifts, d_errs, d_trace, false, (hipStream_t)stream);
+}
+
+size_t mtb_stack_bytemaps_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t levels)
+{
+    Geometry g;
+    if (n < 1 || n > kMaxStack || !make_geometry(width, height, levels, &g))
+        return 0;
+    return (size_t)(set_workspace_bytes(g, n, n - 1, true) + kAlign);
+}
+
+mtb_status mtb_align_stack_bytemaps(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,
+                                    int32_t height, int64_t row_stride, int32_t levels,
+                                    int32_t exclude_range, int32_t ref_index, void *d_workspace,
+                                    size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                                    uint32_t *d_trace, void *stream)
+{
+    return align_stack(h_d_rgb, n, width, height, row_stride, levels, exclude_range, ref_index, d_workspace,
+                       workspace_bytes, d_shifts, d_errs, d_trace, false, (hipStream_t)stream, true);
 }
 
 mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int32_t width,

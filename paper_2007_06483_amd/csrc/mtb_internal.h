@@ -37,6 +37,8 @@ struct LevelGeom {
     int64_t gray_pitch;   // bytes = 64 * wpr, a multiple of 128
     int64_t tb_off;       // bytes, bitmaps buffer
     int64_t eb_off;       // bytes, bitmaps buffer
+    int64_t bt_off;       // bytes, byte-maps buffer: T as 255/0 bytes, rows of gray_pitch
+    int64_t be_off;       // bytes, byte-maps buffer: E likewise
 };
 
 struct Geometry {
@@ -46,6 +48,8 @@ struct Geometry {
     int64_t pyramid_bytes;
     int64_t med_off;        // int32[L] in the bitmaps buffer
     int64_t bitmaps_bytes;
+    int64_t bmed_off;       // int32[L] in the byte-maps buffer
+    int64_t bytemaps_bytes;
 };
 
 // Returns false if the size or level count is out of range.
@@ -177,6 +181,9 @@ hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);
 hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s);
 hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s);
 hipError_t launch_apply(const ApplyArgs &a, int device_cus, hipStream_t s);
+// The byte-map comparison path: T/E as 255/0 bytes, and the search over them.
+hipError_t launch_bytemaps(const BitmapArgs &a, int device_cus, hipStream_t s);
+hipError_t launch_search_bytes(SearchArgs a, int device_cus, hipStream_t s);
 // Turns the pairwise shifts of a chained stack (image i against its neighbour
 // towards ref) into shifts against ref, in place.
 hipError_t launch_chain(int32_t *d_shifts, int n, int ref, hipStream_t s);

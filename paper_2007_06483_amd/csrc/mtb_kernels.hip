@@ -577,6 +577,78 @@ __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
     }
 }
 
+// The paper's representation, for comparison: T and E as one byte per pixel
+// (255 or 0), rows of gray_pitch bytes, padding bytes 0.  Same chunk walk as
+// k_bitmaps; lane i turns bytes [32 i, 32 i + 32) of a chunk into 32 T bytes
+// and 32 E bytes with the byte-wise comparisons of ByteGe.
+__global__ __launch_bounds__(256) void k_bytemaps(BitmapArgs a)
+{
+    const int wave = wave_id();
+    const int lane = threadIdx.x & 63;
+    const Geometry &g = a.g;
+    const int64_t per_image = a.chunk_start[g.L];
+    const int64_t total = per_image * a.n;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t per_wave = (total + nwaves - 1) / nwaves;
+    const int64_t c0 = gw * per_wave;
+    const int64_t c1 = c0 + per_wave < total ? c0 + per_wave : total;
+    if (c0 >= c1)
+        return;
+    const uint32_t X = (uint32_t)a.exclude;
+    int cur_img = -1, cur_l = -1;
+    uint32_t m = 0;
+    ByteGe ge_t = byte_ge(0), ge_hi = byte_ge(0), ge_lo = byte_ge(0);
+    uint32_t keep_t = 0, keep_hi = 0;
+    ChunkPos p = chunk_pos(a, c0, per_image);
+    uint4 v0, v1;
+    load_chunk(a, p, lane, v0, v1);
+    for (int64_t c = c0; c < c1; ++c) {
+        const ChunkPos cp = p;
+        const LevelGeom &lv = g.lv[cp.level];
+        if (cp.img != cur_img || cp.level != cur_l) {
+            m = wave_median((const uint32_t *)(a.pyr[cp.img] + g.hist_off) + 256 * cp.level,
+                            (uint32_t)(lv.w * lv.h));
+            cur_img = cp.img;
+            cur_l = cp.level;
+            ge_t = byte_ge(m + 1u);
+            keep_t = m < 255u ? ~0u : 0u;
+            ge_hi = byte_ge(m + X + 1u);
+            keep_hi = m + X < 255u ? ~0u : 0u;
+            ge_lo = byte_ge(m > X ? m - X : 0u);
+        }
+        if (cp.w0 == 0 && lane == 0)
+            ((int32_t *)(a.bm[cp.img] + g.bmed_off))[cp.level] = (int32_t)m;
+        const uint32_t d[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        if (c + 1 < c1) {
+            p = chunk_pos(a, c + 1, per_image);
+            load_chunk(a, p, lane, v0, v1);
+        }
+        // Valid bytes of the lane's 32 (columns below the level width).
+        const int nvalid = lv.w - 64 * ((cp.w0 + (lane >> 1)) % lv.wpr) - 32 * (lane & 1);
+        uint32_t t[8], e[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t xh = d[k] | 0x80808080u;
+            const uint32_t rt = ge_bytes(d[k], xh, ge_t) & keep_t;
+            const uint32_t re = (ge_bytes(d[k], xh, ge_hi) & keep_hi) | ~ge_bytes(d[k], xh, ge_lo);
+            const int cnt = nvalid - 4 * k;
+            const uint32_t keep = cnt >= 4 ? ~0u : (cnt <= 0 ? 0u : (1u << (8 * cnt)) - 1u);
+            t[k] = (((rt >> 7) & 0x01010101u) * 0xffu) & keep;
+            e[k] = (((re >> 7) & 0x01010101u) * 0xffu) & keep;
+        }
+        if (lane < 2 * cp.cnt) {
+            const int64_t off = (int64_t)cp.w0 * 64 + lane * 32;
+            uint4 *tb = (uint4 *)(a.bm[cp.img] + lv.bt_off + off);
+            uint4 *eb = (uint4 *)(a.bm[cp.img] + lv.be_off + off);
+            tb[0] = make_uint4(t[0], t[1], t[2], t[3]);
+            tb[1] = make_uint4(t[4], t[5], t[6], t[7]);
+            eb[0] = make_uint4(e[0], e[1], e[2], e[3]);
+            eb[1] = make_uint4(e[4], e[5], e[6], e[7]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- search
 
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t sh)
@@ -1094,23 +1166,19 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
         coarse_walk(a, threadIdx.x, ssurf + threadIdx.x * kSurfWords, true);
 }
 
-// One level below the coarse ones, for every pair: grid (workgroups per pair, pairs).
-__global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
+// This level's base (twice the winner of the level above, or the coarse walk's
+// result, or 0 at the top) into sbase[0..1] in LDS; one round trip.  Called by
+// every thread of the workgroup; ends with a workgroup barrier.
+__device__ __forceinline__ void level_base(const SearchArgs &a, int pair, int *sbase)
 {
     __shared__ uint32_t cnt[kSurfWords > kCounterWords ? kSurfWords : kCounterWords];
     __shared__ uint32_t tot[9];
     __shared__ int sprev[2];
-    __shared__ int sbase[2];
-    __shared__ uint32_t red[4][9];
-    const int pair = blockIdx.y;
-    const int wave = wave_id();
-    const int lane = threadIdx.x & 63;
     const Geometry &g = a.g;
     const int l = a.level;
     uint32_t *state = pair_state(a, pair);
     int32_t *bases = pair_bases(a, pair);
 
-    // Base of this level = twice the winner of the level above (one round trip).
     if (a.coarse_n > 0 && l == g.L - 1 - a.coarse_n) {
         // First level after the coarse ones: walk their surfaces.
         const uint32_t *surf = pair_surface(a, pair);
@@ -1170,14 +1238,15 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
         store_shared((uint32_t *)bases, (uint32_t)sbase[0]);
         store_shared((uint32_t *)bases + 1, (uint32_t)sbase[1]);
     }
+}
 
-    const LevelGeom &lv = g.lv[l];
-    const UnitPlan p = plan_level(lv, a.rows_per_stream);
-    uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int unit = blockIdx.x * 4 + wave;
-    if (unit < p.units)
-        search_unit(a.ref[pair], a.mov[pair], lv, sbase[0], sbase[1], unit, p.cw_log2, a.rows_per_stream,
-                    p.units_x, acc);
+// Sums the workgroup's nine errors into this level's counters (copy
+// blockIdx.x % kCopies); at level 0 the last workgroup writes the outputs.
+__device__ __forceinline__ void level_finish(const SearchArgs &a, int pair, const uint32_t *acc)
+{
+    __shared__ uint32_t red[4][9];
+    const int wave = wave_id();
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const uint32_t s = wave_sum(acc[i]);
@@ -1189,10 +1258,130 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
         const uint32_t s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
                            red[3][threadIdx.x];
         if (s)
-            atomicAdd(state + l * kCounterWords + (blockIdx.x % kCopies) * 9 + threadIdx.x, s);
+            atomicAdd(pair_state(a, pair) + a.level * kCounterWords + (blockIdx.x % kCopies) * 9 + threadIdx.x, s);
     }
-    if (l == 0 && last_workgroup(a.done + kTicketGroups + 1))
+    if (a.level == 0 && last_workgroup(a.done + kTicketGroups + 1))
         finalize_level0(a);
+}
+
+// One level below the coarse ones, for every pair: grid (workgroups per pair, pairs).
+__global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
+{
+    __shared__ int sbase[2];
+    const int pair = blockIdx.y;
+    level_base(a, pair, sbase);
+    const LevelGeom &lv = a.g.lv[a.level];
+    const UnitPlan p = plan_level(lv, a.rows_per_stream);
+    uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int unit = blockIdx.x * 4 + wave_id();
+    if (unit < p.units)
+        search_unit(a.ref[pair], a.mov[pair], lv, sbase[0], sbase[1], unit, p.cw_log2, a.rows_per_stream,
+                    p.units_x, acc);
+    level_finish(a, pair, acc);
+}
+
+// Byte-map search (comparison path): each lane owns one dword (four pixels) of
+// a reference row; a wavefront covers 64 dwords x `rows` rows.  The three
+// horizontal shifts of a moving dword come from v_alignbyte over three
+// consecutive dwords, the vertical ones from a window of three moving rows;
+// each set byte of (T_r ^ S T_m) & E_r & S E_m holds 8 set bits, so the sums
+// are divided by 8 at the end.  Loads are clamped and exclusion bytes masked
+// as in the packed search.
+__device__ void search_unit_bytes(const uint8_t *ref, const uint8_t *mov, const LevelGeom &lv, int bx, int by,
+                                  int unit, int rows, int units_x, uint32_t acc[9])
+{
+    const int lane = threadIdx.x & 63;
+    const int ncol = (int)(lv.gray_pitch / 4);  // dwords per row
+    const int h = lv.h;
+    const int sx = unit % units_x, sy = unit / units_x;
+    const int k = sx * kWave + lane;
+    const int y_begin = sy * rows;
+    const int y_end = y_begin + rows < h ? y_begin + rows : h;
+    const uint8_t *tr = ref + lv.bt_off, *er = ref + lv.be_off;
+    const int64_t rb = lv.gray_pitch;
+    const int u = -bx - 1;
+    const int q = k + (u >> 2);  // floor((4k - bx - 1) / 4)
+    const uint32_t r = (uint32_t)u & 3u;
+    const uint32_t kref = 4u * (uint32_t)(k < ncol ? k : ncol - 1);
+    const uint32_t ref_ok = (k < ncol && y_begin < h) ? ~0u : 0u;
+    const int qc = q < -2 ? -2 : (q > ncol - 1 ? ncol - 1 : q);
+    const uint32_t coff = 4u * (uint32_t)(qc + 2);
+    uint32_t cmask[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        cmask[i] = (q + i >= 0 && q + i < ncol) ? ~0u : 0u;
+    const uint8_t *tmg = mov + lv.bt_off - 8, *emg = mov + lv.be_off - 8;
+    // Shifted moving dwords of row j for ddx = -1, 0, +1 (index 0, 1, 2).
+    auto moving = [&](int j, uint32_t *st, uint32_t *se) {
+        const int jc = j < 0 ? 0 : (j >= h ? h - 1 : j);
+        const uint32_t rmask = j == jc ? ~0u : 0u;
+        const uint32_t off = (uint32_t)jc * (uint32_t)rb + coff;
+        uint32_t wt[3], we[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            wt[i] = *(const uint32_t *)(tmg + off + 4 * i);
+            we[i] = *(const uint32_t *)(emg + off + 4 * i) & cmask[i] & rmask;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const uint32_t o = r + 2u - (uint32_t)d;  // byte offset of shift ddx = d - 1 in the window
+            const uint32_t lo = o >> 2, sh = o & 3u;
+            st[d] = __builtin_amdgcn_alignbyte(lo ? wt[2] : wt[1], lo ? wt[1] : wt[0], sh);
+            se[d] = __builtin_amdgcn_alignbyte(lo ? we[2] : we[1], lo ? we[1] : we[0], sh);
+        }
+    };
+    uint32_t at[3], ae[3], bt[3], be[3];
+    moving(y_begin - by + 1, at, ae);  // rotated below: a = ddy + 1 row, b = ddy 0 row
+    moving(y_begin - by, bt, be);
+    // Window: c* = row y - by + 1 (ddy = -1), b* = y - by (0), a* = y - by - 1 (+1).
+    uint32_t ct[3], ce[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ct[d] = at[d];
+        ce[d] = ae[d];
+    }
+    moving(y_begin - by - 1, at, ae);
+    for (int y = y_begin; y < y_begin + rows; ++y) {
+        const int yy = y < y_end ? y : y_end - 1;
+        const uint32_t ok = y < y_end ? ref_ok : 0u;
+        const uint32_t t0 = *(const uint32_t *)(tr + (uint32_t)yy * (uint32_t)rb + kref);
+        const uint32_t e0 = *(const uint32_t *)(er + (uint32_t)yy * (uint32_t)rb + kref) & ok;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            acc[d] += __builtin_popcount((t0 ^ ct[d]) & e0 & ce[d]);      // ddy = -1
+            acc[3 + d] += __builtin_popcount((t0 ^ bt[d]) & e0 & be[d]);  // ddy = 0
+            acc[6 + d] += __builtin_popcount((t0 ^ at[d]) & e0 & ae[d]);  // ddy = +1
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            at[d] = bt[d];
+            ae[d] = be[d];
+            bt[d] = ct[d];
+            be[d] = ce[d];
+        }
+        moving(y + 1 - by + 1, ct, ce);
+    }
+}
+
+// One level of the byte-map search for every pair: grid (workgroups per pair, pairs).
+__global__ __launch_bounds__(256) void k_search_bytes(SearchArgs a)
+{
+    __shared__ int sbase[2];
+    const int pair = blockIdx.y;
+    level_base(a, pair, sbase);
+    const LevelGeom &lv = a.g.lv[a.level];
+    const int ncol = (int)(lv.gray_pitch / 4);
+    const int units_x = (ncol + kWave - 1) / kWave;
+    const int units = units_x * ((lv.h + a.rows_per_stream - 1) / a.rows_per_stream);
+    uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int unit = blockIdx.x * 4 + wave_id();
+    if (unit < units)
+        search_unit_bytes(a.ref[pair], a.mov[pair], lv, sbase[0], sbase[1], unit, a.rows_per_stream, units_x,
+                          acc);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        acc[i] >>= 3;  // eight set bits per counted pixel
+    level_finish(a, pair, acc);
 }
 
 // ---------------------------------------------------------------- apply shifts
@@ -1382,6 +1571,40 @@ hipError_t launch_apply(const ApplyArgs &a, int cus, hipStream_t s)
     const int64_t cap = (int64_t)cus * 64;
     const int64_t blocks = rows < cap ? rows : cap;
     return launch_kernel("k_apply", k_apply, dim3((unsigned)blocks), dim3(256), s, a);
+}
+
+hipError_t launch_bytemaps(const BitmapArgs &a, int cus, hipStream_t s)
+{
+    const int64_t total = a.chunk_start[a.g.L] * a.n;
+    int64_t blocks = (total + 3) / 4;
+    const int64_t cap = (int64_t)cus * resident_per_cu(k_bytemaps);
+    blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
+    return launch_kernel("k_bytemaps", k_bytemaps, dim3((unsigned)blocks), dim3(256), s, a);
+}
+
+hipError_t launch_search_bytes(SearchArgs a, int cus, hipStream_t s)
+{
+    const Geometry &g = a.g;
+    a.coarse_n = 0;
+    const int64_t resident = (int64_t)cus * resident_per_cu(k_search_bytes);
+    for (int l = g.L - 1; l >= 0; --l) {
+        const LevelGeom &lv = g.lv[l];
+        const int units_x = (int)((lv.gray_pitch / 4 + kWave - 1) / kWave);
+        auto blocks_for = [&](int rows) {
+            const int units = units_x * ((lv.h + rows - 1) / rows);
+            return ((units + 3) / 4 + kXcds - 1) / kXcds * kXcds;
+        };
+        int rows = 4;
+        while (rows < 256 && (int64_t)blocks_for(rows) * a.npairs > resident)
+            rows += 4;
+        a.level = l;
+        a.rows_per_stream = rows;
+        const hipError_t e = launch_kernel("k_search_bytes", k_search_bytes, dim3(blocks_for(rows), a.npairs),
+                                           dim3(256), s, a);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
