@@ -866,12 +866,36 @@ __device__ __forceinline__ void search_unit(const uint8_t *ref, const uint8_t *m
         search_unit_t<2>(ref, mov, lv, bx, by, unit, cw_log2, rows, units_x, acc);
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+// Sums each of v[0..N) over the wavefront (every lane gets the totals).
+// Within each row of 16 lanes, DPP moves (no LDS): swap neighbours, swap
+// pairs (quad permutes), mirror each half-row, mirror the row — after which
+// every lane holds its row's sum; the last two steps cross rows with
+// ds_bpermute, the N exchanges of a step all in flight at once.
+template <int N>
+__device__ __forceinline__ void wave_sums(uint32_t *v)
 {
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1)
-        v += __shfl_xor(v, d);
-    return v;
+    for (int i = 0; i < N; ++i)  // quad_perm [1,0,3,2]
+        v[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[i], 0xb1, 0xf, 0xf, true);
+#pragma unroll
+    for (int i = 0; i < N; ++i)  // quad_perm [2,3,0,1]
+        v[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[i], 0x4e, 0xf, 0xf, true);
+#pragma unroll
+    for (int i = 0; i < N; ++i)  // row_half_mirror
+        v[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[i], 0x141, 0xf, 0xf, true);
+#pragma unroll
+    for (int i = 0; i < N; ++i)  // row_mirror
+        v[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[i], 0x140, 0xf, 0xf, true);
+#pragma unroll
+    for (int d = 16; d <= 32; d <<= 1) {
+        uint32_t o[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            o[i] = __shfl_xor(v[i], d);
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            v[i] += o[i];
+    }
 }
 
 // First minimum in ddy-major order; returns the candidate index 0..8.
@@ -1126,12 +1150,11 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
             }
         }
     }
+    wave_sums<2 * kMaxR + 1>(acc);
+    if (lane == 0)
 #pragma unroll
-    for (int c = 0; c < 2 * kMaxR + 1; ++c) {
-        const uint32_t s = wave_sum(acc[c]);
-        if (lane == 0)
-            red[wave][c] = s;
-    }
+        for (int c = 0; c < 2 * kMaxR + 1; ++c)
+            red[wave][c] = acc[c];
     __syncthreads();
     uint32_t *surf = pair_surface(a, pair) + coarse_surface_offset(i);
     if ((int)threadIdx.x < 2 * R + 1) {
@@ -1247,12 +1270,15 @@ __device__ __forceinline__ void level_finish(const SearchArgs &a, int pair, cons
     __shared__ uint32_t red[4][9];
     const int wave = wave_id();
     const int lane = threadIdx.x & 63;
+    uint32_t v[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const uint32_t s = wave_sum(acc[i]);
-        if (lane == 0)
-            red[wave][i] = s;
-    }
+    for (int i = 0; i < 9; ++i)
+        v[i] = acc[i];
+    wave_sums<9>(v);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            red[wave][i] = v[i];
     __syncthreads();
     if (threadIdx.x < 9) {
         const uint32_t s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
