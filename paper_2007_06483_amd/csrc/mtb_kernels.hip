@@ -94,11 +94,17 @@ __device__ __forceinline__ void load_rgb16(const uint8_t *rgb, int64_t stride, i
     }
 }
 
+// Tiles whose levels 5 and 6 wait in an LDS ring; the ring is drained by the
+// whole workgroup after one barrier, instead of one barrier per tile.
+constexpr int kDefer = 8;
+
 // Workgroup tile: kTileH = 64 rows x kTileW = 256 columns of level 0.  Wave w
 // owns rows 16w .. 16w+15; lane (bx = lane & 15, by = lane >> 4) owns the
 // 4-row x 16-column block at (X0 + 16 bx, Y0 + 16 w + 4 by).  Levels 1 and 2
 // stay inside the lane, levels 3 and 4 combine lanes of the wave with
-// shuffles, levels 5 and 6 combine the four waves through LDS.  Each lane
+// shuffles, levels 5 and 6 combine the four waves through LDS: a tile's 4 x 16
+// level-4 pixels are parked in a ring of kDefer tiles, and a full ring is
+// turned into levels 5 and 6 by all 256 threads at once.  Each lane
 // reads 4 x 48 bytes of RGB per tile (a row of 16 lanes covers 768
 // contiguous bytes), and with 16-byte aligned rows the next tile's RGB is
 // loaded while the current one is processed.
@@ -107,7 +113,8 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     __shared__ uint32_t hist0[4 * kH0Copies * kHStride];  // level 0, per wave and lane group
     __shared__ uint32_t hist1[4][256];                    // level 1, per wave
     __shared__ uint32_t histc[kFused - 2][256];           // levels 2 .. 6, whole workgroup
-    __shared__ uint32_t lvl4[2][4][16];                   // level-4 pixels of a tile, by tile parity
+    __shared__ uint32_t lvl4[2][kDefer][4][16];           // level-4 pixels of deferred tiles, two rings
+    __shared__ int2 ring_pos[2][kDefer];                  // level-0 origin of each deferred tile
 
     const int tid = threadIdx.x;
     const int wave = wave_id();
@@ -138,8 +145,54 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     const int64_t t0 = xb + slot;
     const int64_t t1 = xb + a.xcd_tiles < total ? xb + a.xcd_tiles : total;
 
+    // Levels 5 and 6 of the `count` tiles parked in ring `bank` (image img).
+    // Call after a barrier that follows the tiles' level-4 writes; thread
+    // tid takes pixel tid % 20 of ring entry tid / 20 (16 level-5 pixels in
+    // 2 rows of 8, then 4 level-6 pixels).
+    auto drain = [&](int img, int bank, int count) {
+        const int k = tid / 20, r = tid - 20 * (tid / 20);
+        if (k >= count)
+            return;
+        const uint32_t(*qq)[16] = lvl4[bank][k];
+        const int2 o = ring_pos[bank][k];
+        uint8_t *pyr = a.pyr[img];
+        if (r < 16) {
+            const int i5 = r >> 3, j5 = r & 7;
+            const uint32_t u5 = (qq[2 * i5][2 * j5] + qq[2 * i5][2 * j5 + 1] + qq[2 * i5 + 1][2 * j5] +
+                                 qq[2 * i5 + 1][2 * j5 + 1]) >> 2;
+            const LevelGeom &l5 = g.lv[5];
+            const int x5 = (o.x >> 5) + j5, y5 = (o.y >> 5) + i5;
+            if (y5 < l5.h && x5 < l5.w) {
+                pyr[l5.gray_off + (int64_t)y5 * l5.gray_pitch + x5] = (uint8_t)u5;
+                atomicAdd(&histc[3][u5], 1u);
+            }
+        } else if (fused > 6) {
+            const int j6 = r - 16;
+            uint32_t s6 = 0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 2 * j6; j < 2 * j6 + 2; ++j)
+                    s6 += (qq[2 * i][2 * j] + qq[2 * i][2 * j + 1] + qq[2 * i + 1][2 * j] +
+                           qq[2 * i + 1][2 * j + 1]) >> 2;
+            const uint32_t u6 = s6 >> 2;
+            const LevelGeom &l6 = g.lv[6];
+            const int x6 = (o.x >> 6) + j6, y6 = o.y >> 6;
+            if (y6 < l6.h && x6 < l6.w) {
+                pyr[l6.gray_off + (int64_t)y6 * l6.gray_pitch + x6] = (uint8_t)u6;
+                atomicAdd(&histc[4][u6], 1u);
+            }
+        }
+    };
+    int bank = 0, parked = 0;
+
     auto flush = [&](int img) {
         __syncthreads();
+        if (parked > 0) {
+            drain(img, bank, parked);
+            parked = 0;
+            __syncthreads();
+        }
         uint32_t *gh = (uint32_t *)(a.pyr[img] + g.hist_off);
         for (int l = 0; l < fused; ++l) {
             uint32_t s = 0;
@@ -180,7 +233,6 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     }
 
     int cur = -1;
-    int parity = 0;
     for (int64_t t = t0; t < t1; t += slots) {
         int img, X0, Y0;
         locate(t, img, X0, Y0);
@@ -328,40 +380,18 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
                             atomicAdd(&histc[2][u4], 1u);
                         }
                         if (fused > 5) {
-                            // ---- levels 5 and 6: the tile holds 4 x 16 level-4 pixels
-                            // (row = wave, column = bx).
+                            // ---- levels 5 and 6: park the tile's 4 x 16 level-4 pixels
+                            // (row = wave, column = bx); a full ring is drained.
                             if (by == 0)
-                                lvl4[parity][wave][bx] = u4;
-                            __syncthreads();
-                            const uint32_t(*qq)[16] = lvl4[parity];
-                            if (tid < 16) {
-                                const int i5 = tid >> 3, j5 = tid & 7;
-                                const uint32_t u5 = (qq[2 * i5][2 * j5] + qq[2 * i5][2 * j5 + 1] +
-                                                     qq[2 * i5 + 1][2 * j5] + qq[2 * i5 + 1][2 * j5 + 1]) >> 2;
-                                const LevelGeom &l5 = g.lv[5];
-                                const int x5 = (X0 >> 5) + j5, y5 = (Y0 >> 5) + i5;
-                                if (y5 < l5.h && x5 < l5.w) {
-                                    pyr[l5.gray_off + (int64_t)y5 * l5.gray_pitch + x5] = (uint8_t)u5;
-                                    atomicAdd(&histc[3][u5], 1u);
-                                }
-                            } else if (fused > 6 && tid >= 64 && tid < 68) {
-                                const int j6 = tid - 64;
-                                uint32_t s6 = 0;
-#pragma unroll
-                                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                                    for (int j = 2 * j6; j < 2 * j6 + 2; ++j)
-                                        s6 += (qq[2 * i][2 * j] + qq[2 * i][2 * j + 1] + qq[2 * i + 1][2 * j] +
-                                               qq[2 * i + 1][2 * j + 1]) >> 2;
-                                const uint32_t u6 = s6 >> 2;
-                                const LevelGeom &l6 = g.lv[6];
-                                const int x6 = (X0 >> 6) + j6, y6 = Y0 >> 6;
-                                if (y6 < l6.h && x6 < l6.w) {
-                                    pyr[l6.gray_off + (int64_t)y6 * l6.gray_pitch + x6] = (uint8_t)u6;
-                                    atomicAdd(&histc[4][u6], 1u);
-                                }
+                                lvl4[bank][parked][wave][bx] = u4;
+                            if (tid == 0)
+                                ring_pos[bank][parked] = make_int2(X0, Y0);
+                            if (++parked == kDefer) {
+                                __syncthreads();
+                                drain(img, bank, kDefer);
+                                bank ^= 1;
+                                parked = 0;
                             }
-                            parity ^= 1;
                         }
                     }
                 }
