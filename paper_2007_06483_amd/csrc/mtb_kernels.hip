@@ -76,6 +76,9 @@ __device__ __forceinline__ uint32_t pack4(const uint32_t *v)
 constexpr int kH0Copies = 8;
 constexpr int kHStride = 257;
 
+// Clang vector type, the operand type the nontemporal builtins accept.
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+
 // Loads one lane's 4 rows x 48 bytes (16 pixels) of RGB with 16-byte loads;
 // rows at or below H read as zero.
 __device__ __forceinline__ void load_rgb16(const uint8_t *rgb, int64_t stride, int x0, int y0, int H,
@@ -298,8 +301,14 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
                 const int y = y0 + rr;
                 if (y < g.H && x0 < g.W) {
                     // x0 % 16 == 0, x0 < W <= pitch, pitch % 64 == 0: 16 bytes inside the row.
-                    *(uint4 *)(pyr + lv.gray_off + (int64_t)y * lv.gray_pitch + x0) =
-                        make_uint4(pack4(&gv[rr][0]), pack4(&gv[rr][4]), pack4(&gv[rr][8]), pack4(&gv[rr][12]));
+                    // Streaming (nontemporal) store: level 0 is read again only by the
+                    // next kernel, and keeping it out of L2 speeds up the RGB stream.
+                    U32x4 v;
+                    v.x = pack4(&gv[rr][0]);
+                    v.y = pack4(&gv[rr][4]);
+                    v.z = pack4(&gv[rr][8]);
+                    v.w = pack4(&gv[rr][12]);
+                    __builtin_nontemporal_store(v, (U32x4 *)(pyr + lv.gray_off + (int64_t)y * lv.gray_pitch + x0));
                     if (full) {
 #pragma unroll
                         for (int c = 0; c < 16; ++c)
@@ -482,6 +491,32 @@ __device__ __forceinline__ ChunkPos chunk_pos(const BitmapArgs &a, int64_t c, in
     return p;
 }
 
+// The chunk after p, and col0 = p.w0 mod wpr of its level, without divisions
+// (every level holds at least one word).
+__device__ __forceinline__ void next_chunk(const BitmapArgs &a, ChunkPos &p, int &col0)
+{
+    const LevelGeom *lv = &a.g.lv[p.level];
+    p.w0 += kChunkWords;
+    int nwords = lv->h * lv->wpr;
+    if (p.w0 >= nwords) {
+        p.w0 = 0;
+        col0 = 0;
+        if (++p.level == a.g.L) {
+            p.level = 0;
+            ++p.img;
+        }
+        lv = &a.g.lv[p.level];
+        nwords = lv->h * lv->wpr;
+    } else if (lv->wpr >= kChunkWords) {
+        col0 += kChunkWords;
+        if (col0 >= lv->wpr)
+            col0 -= lv->wpr;
+    } else {
+        col0 = (col0 + kChunkWords) % lv->wpr;
+    }
+    p.cnt = nwords - p.w0 < kChunkWords ? nwords - p.w0 : kChunkWords;
+}
+
 // Lane i's 32 pixels of a chunk: bytes [32 i, 32 i + 32), zero past the chunk.
 __device__ __forceinline__ void load_chunk(const BitmapArgs &a, const ChunkPos &p, int lane, uint4 &v0, uint4 &v1)
 {
@@ -529,6 +564,48 @@ __device__ __forceinline__ void transpose8(const uint32_t *d, uint32_t *t)
     }
 }
 
+// The three thresholds of a level, T: m + 1, E: m + X + 1 and max(m - X, 0),
+// as byte-wise comparison constants; keep_* clear a threshold above 255.
+struct Thresholds {
+    uint32_t low_t, low_hi, low_lo, keep_t, keep_hi;
+    int nlow;  // how many thresholds are below 128 (lo <= t <= hi, so a prefix)
+};
+__device__ __forceinline__ Thresholds thresholds(uint32_t m, uint32_t X)
+{
+    const uint32_t yt = m + 1u, yhi = m + X + 1u, ylo = m > X ? m - X : 0u;
+    Thresholds c;
+    c.low_t = (yt & 0x7fu) * 0x01010101u;
+    c.low_hi = (yhi & 0x7fu) * 0x01010101u;
+    c.low_lo = (ylo & 0x7fu) * 0x01010101u;
+    c.keep_t = yt < 256u ? ~0u : 0u;
+    c.keep_hi = yhi < 256u ? ~0u : 0u;
+    c.nlow = (ylo < 128u) + (yt < 128u) + (yhi < 128u);
+    return c;
+}
+
+// T and E bits of a lane's 32 transposed pixels (byte b of t[k] = pixel 8b + k)
+// with ge_bytes specialised on which thresholds are below 128: x >= y is bit 7
+// of x | d for y < 128 and of x & d otherwise (d = (x | 0x80808080) - low).
+// Bit 7 of byte b of each answer moves to bit 8b + k of the word.
+template <bool kLowT, bool kLowHi, bool kLowLo>
+__device__ __forceinline__ void te_bits(const uint32_t (&t)[8], const Thresholds &c, uint32_t &tw, uint32_t &ew)
+{
+    tw = 0u;
+    ew = 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t x = t[k], xh = x | 0x80808080u;
+        const uint32_t dt = xh - c.low_t, dhi = xh - c.low_hi, dlo = xh - c.low_lo;
+        const uint32_t gt = kLowT ? (x | dt) : (x & dt);
+        const uint32_t ghi = kLowHi ? (x | dhi) : (x & dhi);
+        const uint32_t glo = kLowLo ? (x | dlo) : (x & dlo);
+        const uint32_t rt = gt & c.keep_t;
+        const uint32_t re = (ghi & c.keep_hi) | ~glo;
+        tw |= (rt >> (7 - k)) & (0x01010101u << k);
+        ew |= (re >> (7 - k)) & (0x01010101u << k);
+    }
+}
+
 // Each wavefront walks a contiguous run of chunks of kChunkWords = 32
 // consecutive 64-pixel words of one level (the next chunk's loads are issued
 // before the current one is processed).  Lane i takes the chunk's bytes
@@ -555,13 +632,14 @@ __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
 
     int cur_img = -1, cur_l = -1;
     uint32_t m = 0;
-    ByteGe ge_t = byte_ge(0), ge_hi = byte_ge(0), ge_lo = byte_ge(0);
-    uint32_t keep_t = 0, keep_hi = 0;
+    Thresholds th = thresholds(0u, X);
     ChunkPos p = chunk_pos(a, c0, per_image);
+    int col0 = p.w0 % g.lv[p.level].wpr;
     uint4 v0, v1;
     load_chunk(a, p, lane, v0, v1);
     for (int64_t c = c0; c < c1; ++c) {
         const ChunkPos cp = p;
+        const int ccol0 = col0;
         const LevelGeom &lv = g.lv[cp.level];
         if (cp.img != cur_img || cp.level != cur_l) {
             m = wave_median((const uint32_t *)(a.pyr[cp.img] + g.hist_off) + 256 * cp.level,
@@ -569,36 +647,33 @@ __global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
             cur_img = cp.img;
             cur_l = cp.level;
             // T = [g >= m + 1]; E = [g >= m + X + 1] | ~[g >= max(m - X, 0)].
-            // A threshold above 255 is never reached: its bits are cleared.
-            ge_t = byte_ge(m + 1u);
-            keep_t = m < 255u ? ~0u : 0u;
-            ge_hi = byte_ge(m + X + 1u);
-            keep_hi = m + X < 255u ? ~0u : 0u;
-            ge_lo = byte_ge(m > X ? m - X : 0u);
+            th = thresholds(m, X);
         }
         if (cp.w0 == 0 && lane == 0)
             ((int32_t *)(a.bm[cp.img] + g.med_off))[cp.level] = (int32_t)m;
 
         const uint32_t d[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
         if (c + 1 < c1) {
-            p = chunk_pos(a, c + 1, per_image);
+            next_chunk(a, p, col0);
             load_chunk(a, p, lane, v0, v1);
         }
         uint32_t t[8];
         transpose8(d, t);
-        uint32_t tw = 0, ew = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t xh = t[k] | 0x80808080u;
-            const uint32_t rt = ge_bytes(t[k], xh, ge_t) & keep_t;
-            const uint32_t re = (ge_bytes(t[k], xh, ge_hi) & keep_hi) | ~ge_bytes(t[k], xh, ge_lo);
-            // Bit 7 of byte b is pixel 8b + k: move it to bit 8b + k.
-            tw |= (rt >> (7 - k)) & (0x01010101u << k);
-            ew |= (re >> (7 - k)) & (0x01010101u << k);
+        uint32_t tw, ew;
+        switch (th.nlow) {
+        case 0: te_bits<false, false, false>(t, th, tw, ew); break;
+        case 1: te_bits<false, false, true>(t, th, tw, ew); break;
+        case 2: te_bits<true, false, true>(t, th, tw, ew); break;
+        default: te_bits<true, true, true>(t, th, tw, ew); break;
         }
         // Bits past the level width are zero: lane i holds half-word i % 2 of
         // word w0 + i / 2, whose pixels start at column 64 * ((w0 + i / 2) mod wpr).
-        const int nbits = lv.w - 64 * ((cp.w0 + (lane >> 1)) % lv.wpr) - 32 * (lane & 1);
+        int col = ccol0 + (lane >> 1);
+        if (lv.wpr >= kChunkWords)
+            col = col >= lv.wpr ? col - lv.wpr : col;
+        else
+            col = col % lv.wpr;
+        const int nbits = lv.w - 64 * col - 32 * (lane & 1);
         const uint32_t keep = nbits >= 32 ? ~0u : (nbits <= 0 ? 0u : (1u << nbits) - 1u);
         if (lane < 2 * cp.cnt) {
             ((uint32_t *)(a.bm[cp.img] + lv.tb_off))[2 * (int64_t)cp.w0 + lane] = tw & keep;
