@@ -93,12 +93,24 @@ def cpu_baseline(imgs, levels, ref, mp_total, max_threads, min_seconds, chained=
     run = oracle.align_stack_chained if chained else oracle.align_stack
     threads = max(1, min(max_threads, len(imgs), os.cpu_count() or 1))
     reps = 0
+    runs_ms = []
     t0 = time.perf_counter()
     while True:
+        t = time.perf_counter()
         out = run(imgs, levels, ref_index=ref, threads=threads)
+        runs_ms.append((time.perf_counter() - t) * 1e3)
         reps += 1
         dt = time.perf_counter() - t0
         if dt >= min_seconds:
+            break
+    runs_ms.sort()
+    # One thread, a bounded sample: whole alignments for about a quarter of the time above.
+    one, t1 = 0, time.perf_counter()
+    while True:
+        run(imgs, levels, ref_index=ref, threads=1)
+        one += 1
+        dt1 = time.perf_counter() - t1
+        if dt1 >= min_seconds / 4:
             break
     return out, {
         "value": round(reps * mp_total / dt, 3),
@@ -107,7 +119,42 @@ def cpu_baseline(imgs, levels, ref, mp_total, max_threads, min_seconds, chained=
         "kind": "oracle",
         "sample": f"{reps} full alignments of the same {len(imgs)}-image stack ({mp_total:.1f} MP each) "
                   f"in {dt:.2f} s wall, each spreading images, then pairs, over {threads} threads",
+        "run_ms": {"median": round(runs_ms[len(runs_ms) // 2], 1), "min": round(runs_ms[0], 1)},
+        "single_thread": {"value": round(one * mp_total / dt1, 3), "unit": "MP/s",
+                          "sample": f"{one} full alignments on one thread in {dt1:.2f} s"},
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
     }
+
+
+def measured_copy_GBps(torch, dev, nbytes=1 << 30, reps=5):
+    """Achievable HBM rate on this GPU: a plain 1 GiB device-to-device copy
+    (bytes read + bytes written per second, best of `reps`)."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del a, b
+    return 2 * nbytes / best / 1e9
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def pyramid_bytes(W, H, L):
@@ -276,26 +323,32 @@ def run_apply(args, mtb, synth, torch, np, dev):
 
 
 def run_served(args, mtb, synth, torch, np, dev):
-    """Poisson arrivals of exposure stacks served with continuous batching (device-staged:
-    the requests are crops of a base scene resident on the GPU)."""
-    from paper_2007_06483_amd.serving import Request, Server, gpu_executor, percentile
+    """Poisson arrivals of exposure stacks served with continuous batching.
+
+    Device-staged: the requests are crops of a base scene resident on the GPU.
+    Host-staged: the same crops are cut from a copy of the base in pinned host
+    memory and copied to the device (mtb_stage_rgb) inside each request, so
+    their latency includes the host-to-device transfer."""
+    from paper_2007_06483_amd.serving import Request, Server, footprint_bytes, gpu_executor, percentile
 
     BW, BH = 8704, 5888
     log(f"generating the {BW}x{BH} 9-exposure base scene ...")
     t0 = time.perf_counter()
     base = synth.make_serve_base(BW, BH, 5)
     base_dev = [torch.from_numpy(b).to(dev) for b in base]
+    base_host = [torch.from_numpy(b).pin_memory() for b in base] if args.serve_host_seconds > 0 else None
     del base
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
-    def requests(seed, rate, seconds):
+    def requests(seed, rate, seconds, host):
         specs = synth.serve_requests(seed, rate, seconds, BW, BH)
+        src = base_host if host else base_dev
         out = []
         for r in specs:
-            imgs = [synth.serve_crop(base_dev, r, i) for i in range(r["n"])]
+            imgs = [synth.serve_crop(src, r, i) for i in range(r["n"])]
             out.append(Request(rid=r["rid"], arrival=r["arrival"], images=imgs, levels=r["levels"],
-                               workspace_bytes=mtb.mtb_stack_workspace_bytes(r["n"], r["width"], r["height"],
-                                                                             r["levels"]),
+                               workspace_bytes=footprint_bytes(mtb, r["n"], r["width"], r["height"],
+                                                               r["levels"], host),
                                megapixels=r["n"] * r["width"] * r["height"] / 1e6))
         return out
 
@@ -304,17 +357,24 @@ def run_served(args, mtb, synth, torch, np, dev):
     pool = torch.empty(pool_bytes, dtype=torch.uint8, device=dev)
     execute, poll = gpu_executor(pool, slots)
 
-    def serve(rate, seconds, seed):
-        reqs = requests(seed, rate, seconds)
+    def serve(rate, seconds, seed, host=False):
+        reqs = requests(seed, rate, seconds, host)
         srv = Server(pool_bytes, slots, execute, poll)
+        t_run = time.perf_counter()
         res = srv.run(reqs)
         torch.cuda.synchronize()
+        t_run = time.perf_counter() - t_run
         lat = [r.latency * 1e3 for r in res]
         span = max(r.completed for r in res) - min(r.arrival for r in res)
         mp = sum(q.megapixels for q in reqs)
-        return {"offered_per_s": rate, "requests": len(reqs), "p50_ms": round(percentile(lat, 50), 3),
-                "p99_ms": round(percentile(lat, 99), 3), "MPps": round(mp / span, 1),
-                "offered_MPps": round(mp / seconds, 1), "max_in_flight": srv.max_in_flight}
+        out = {"offered_per_s": rate, "requests": len(reqs), "p50_ms": round(percentile(lat, 50), 3),
+               "p99_ms": round(percentile(lat, 99), 3), "MPps": round(mp / span, 1),
+               "offered_MPps": round(mp / seconds, 1), "max_in_flight": srv.max_in_flight,
+               "wall_s": round(t_run, 2)}
+        if host:
+            h2d = sum(3 * q.images[0].shape[0] * q.images[0].shape[1] * len(q.images) for q in reqs)
+            out["h2d_GBps"] = round(h2d / span / 1e9, 2)
+        return out
 
     serve(200.0, 0.5, 99)  # warm-up
     log(f"serving Poisson(200/s) for {args.serve_seconds:.0f} s ...")
@@ -324,6 +384,15 @@ def run_served(args, mtb, synth, torch, np, dev):
     for rate in (800.0, 1600.0, 3200.0, 6400.0):
         sweep.append(serve(rate, 3.0, 50 + int(rate)))
         log(json.dumps(sweep[-1]))
+    host_run, host_sweep = None, []
+    if base_host is not None:
+        serve(200.0, 0.5, 98, host=True)  # warm-up
+        log(f"host-staged: serving Poisson(200/s) for {args.serve_host_seconds:.0f} s ...")
+        host_run = serve(200.0, args.serve_host_seconds, 6, host=True)
+        log(json.dumps(host_run))
+        for rate in (300.0, 400.0):
+            host_sweep.append(serve(rate, 3.0, 60 + int(rate), host=True))
+            log(json.dumps(host_sweep[-1]))
     result = {
         "metric": METRIC,
         "value": main_run["MPps"],
@@ -343,6 +412,8 @@ def run_served(args, mtb, synth, torch, np, dev):
         "latency_ms": {"p50": main_run["p50_ms"], "p99": main_run["p99_ms"]},
         "served": main_run,
         "saturation_sweep": sweep,
+        "host_staged": {"staging": "host (pinned base, mtb_stage_rgb per image inside each request)",
+                        "served": host_run, "saturation_sweep": host_sweep},
     }
     print(json.dumps(result), flush=True)
 
@@ -359,6 +430,8 @@ def main():
                              "served_poisson200", "apply7_6000x4000"])
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
     ap.add_argument("--serve-slots", type=int, default=4, help="served mode: stacks in flight at most")
+    ap.add_argument("--serve-host-seconds", type=float, default=20.0,
+                    help="served mode: length of the host-staged run (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--event-every", type=int, default=4,
                     help="time the dominant kernel with HIP events in every N-th timed step")
@@ -447,6 +520,18 @@ def main():
     torch.cuda.synchronize()
     breakdown = mtb.mtb_profile_end()
 
+    # Distribution of single steps, outside the timed region: each step
+    # bracketed by events on the stream the library launches on.
+    step_us = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        e1.synchronize()
+        step_us.append(e0.elapsed_time(e1) * 1e3)
+    step_us.sort()
+
     gpu_shifts = shifts.cpu().numpy()
     gpu_errs = errs.cpu().numpy().astype(np.int64)
 
@@ -454,6 +539,7 @@ def main():
     launches, total_ms = prof[dominant]
     avg_s = total_ms / launches / 1e3
     achieved = algo[dominant] / avg_s / 1e9
+    copy_gbps = measured_copy_GBps(torch, dev)
     roofline = {
         "bound": "hbm",
         "kernel": dominant,
@@ -465,6 +551,8 @@ def main():
         "avg_launch_us": round(avg_s * 1e6, 2),
         "evented_launches": launches,
         "algorithmic_bytes_per_launch": algo[dominant],
+        "copy_measured": round(copy_gbps, 1),
+        "frac_of_copy": round(achieved / copy_gbps, 4),
     }
 
     # Paper-comparable end-to-end time: host (pinned) -> device copies included.
@@ -516,6 +604,8 @@ def main():
         "hbm_model_bytes_per_step": algo["step"],
         "roofline": roofline,
         "kernels_ms_per_step": {k: round(v[1] / nrep, 4) for k, v in sorted(breakdown.items())},
+        "step_us": {"median": round(step_us[len(step_us) // 2], 1), "min": round(step_us[0], 1),
+                    "max": round(step_us[-1], 1), "steps": len(step_us)},
         "e2e_incl_h2d": {"ms_per_step": round(e2e_ms, 3), "MPps": round(mp_total / (e2e_ms / 1e3), 1)},
     }
 

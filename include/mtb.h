@@ -235,6 +235,27 @@ mtb_status mtb_apply_shifts(const uint8_t *const *h_d_rgb, int32_t n, int32_t wi
                             uint8_t *const *h_d_out, int64_t out_stride, void *stream);
 
 /*
+ * Host-staged input (Section III-B: the exposures are copied from host memory
+ * to the GPU before the pyramids are built): enqueues on `stream` one 2-D
+ * copy of an RGB image from host memory into device memory, row by row
+ * (3 * width bytes of each of `height` rows).  With h_rgb in pinned memory
+ * (hipHostMalloc) the copy is an asynchronous DMA that overlaps kernels on
+ * other streams; with pageable memory it may return only once the copy is
+ * done.  The host buffer must stay valid until the copy has run.  Not a step
+ * of the alignment: plumbing for callers whose frames arrive in host memory.
+ * Speed: with h_rgb, d_rgb, both strides and 3 * width all multiples of 4 the
+ * copy ran at 47-56 GB/s on MI355X over PCIe; a misaligned start address cut
+ * that to about 6 GB/s and a row length that is not a multiple of 4 to under
+ * 1 GB/s (row by row).  Callers staging crops can widen them to whole groups
+ * of four pixels and align a view inside the copy.
+ *   h_rgb, src_stride    host image, rows src_stride >= 3 * width bytes apart
+ *   d_rgb, dst_stride    device destination, rows dst_stride >= 3 * width apart
+ * Errors: MTB_ERR_INVALID_ARG (null pointers, sizes, strides), MTB_ERR_DEVICE.
+ */
+mtb_status mtb_stage_rgb(const uint8_t *h_rgb, int64_t src_stride, int32_t width, int32_t height,
+                         uint8_t *d_rgb, int64_t dst_stride, void *stream);
+
+/*
  * One item of a batch: a reference and a moving RGB image of the same size
  * and row stride (see Images above), aligned with `levels` levels.
  */

@@ -39,6 +39,7 @@ __all__ = [
     "mtb_align_stack_bytemaps",
     "mtb_stack_bytemaps_workspace_bytes",
     "mtb_apply_shifts",
+    "mtb_stage_rgb",
     "mtb_quadrant_workspace_bytes",
     "mtb_align_quadrants",
     "MTB_FILL_ZERO",
@@ -168,6 +169,8 @@ def lib():
     L.mtb_align_quadrants.restype = ctypes.c_int
     L.mtb_apply_shifts.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, P, i32, ctypes.POINTER(P), i64, P]
     L.mtb_apply_shifts.restype = ctypes.c_int
+    L.mtb_stage_rgb.argtypes = [P, i64, i32, i32, P, i64, P]
+    L.mtb_stage_rgb.restype = ctypes.c_int
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
     L.mtb_batch_workspace_bytes.restype = sz
     L.mtb_align_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P]
@@ -384,6 +387,21 @@ def mtb_apply_shifts(images, shifts: torch.Tensor, fill: int = MTB_FILL_ZERO, ou
            lib().mtb_apply_shifts(ins, n, W, H, stride, _ptr(shifts), int(fill), outs, ostride,
                                   _stream(stream)))
     return out
+
+
+def mtb_stage_rgb(host: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:
+    """Enqueue the copy of a host (H, W, 3) RGB image (a view; pinned for an
+    asynchronous copy) into the device image ``dst`` of the same size."""
+    if (not isinstance(host, torch.Tensor) or host.device.type != "cpu" or host.dtype != torch.uint8
+            or host.dim() != 3 or host.shape[2] != 3 or host.stride(2) != 1 or host.stride(1) != 3):
+        raise ValueError("host must be a CPU uint8 (H, W, 3) view with interleaved R,G,B bytes")
+    W, H, dstride = _rgb_geometry(dst)
+    if (int(host.shape[1]), int(host.shape[0])) != (W, H):
+        raise ValueError("host and dst must have the same size")
+    _check("mtb_stage_rgb",
+           lib().mtb_stage_rgb(host.data_ptr(), int(host.stride(0)), W, H, dst.data_ptr(), dstride,
+                               _stream(stream)))
+    return dst
 
 
 def mtb_quadrant_workspace_bytes(width: int, height: int, row_stride: int, levels: int) -> int:

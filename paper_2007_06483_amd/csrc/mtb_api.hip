@@ -604,6 +604,18 @@ mtb_status mtb_apply_shifts(const uint8_t *const *h_d_rgb, int32_t n, int32_t wi
     return device_status(launch_apply(a, cus, (hipStream_t)stream));
 }
 
+mtb_status mtb_stage_rgb(const uint8_t *h_rgb, int64_t src_stride, int32_t width, int32_t height,
+                         uint8_t *d_rgb, int64_t dst_stride, void *stream)
+{
+    if (!h_rgb || !d_rgb || width < 1 || height < 1 || (int64_t)width * height >= ((int64_t)1 << 31))
+        return MTB_ERR_INVALID_ARG;
+    if (src_stride < 3 * (int64_t)width || dst_stride < 3 * (int64_t)width)
+        return MTB_ERR_INVALID_ARG;
+    return device_status(hipMemcpy2DAsync(d_rgb, (size_t)dst_stride, h_rgb, (size_t)src_stride,
+                                          3 * (size_t)width, (size_t)height, hipMemcpyHostToDevice,
+                                          (hipStream_t)stream));
+}
+
 size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items)
 {
     if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH)

@@ -9,6 +9,12 @@ stacks in flight overlap on the device.  Each admitted stack is one
 the serving pool; its pyramids and bitmaps stay on the device.  Latency is
 completion minus arrival.
 
+Requests are device-staged (their images already in device memory) or
+host-staged (their images in host memory, pinned for asynchronous copies):
+a host-staged request's footprint also holds device copies of its images,
+which mtb_stage_rgb fills on the slot's stream before the alignment, so its
+latency includes the host-to-device transfer.
+
 The loop is host logic only: every step of the alignment runs in libmtb's
 kernels.  The executor is a parameter so that the admission and retirement
 logic can be exercised without a GPU.
@@ -185,11 +191,62 @@ def percentile(values, q: float) -> float:
     return v[lo] + (v[hi] - v[lo]) * (pos - lo)
 
 
+STAGE_ALIGN = 256
+
+
+STAGE_WIDEN = 3  # pixels a staged row may gain on either side (see widen_for_dma)
+
+
+def staged_image_bytes(width: int, height: int) -> int:
+    """Device bytes one host-staged RGB image takes in a request's footprint
+    (room for the widening of widen_for_dma)."""
+    return -(-3 * (int(width) + 2 * STAGE_WIDEN) * int(height) // STAGE_ALIGN) * STAGE_ALIGN
+
+
+def widen_for_dma(im):
+    """(view, col): a view of the same rows as the host crop ``im`` widened to
+    whole groups of four pixels of its frame, and the column of ``im`` in it.
+
+    A host-to-device 2-D copy runs at full link speed only when its start
+    addresses, row pitches and row length are multiples of 4 bytes; otherwise
+    it has been measured to go row by row at a tenth of that or less.  A crop
+    of a frame whose rows are a multiple of 4 bytes long starts at byte 3x of a
+    row; widening it to columns [x - x % 4, ceil4(x + w)) makes every offset a
+    multiple of 4.  Returns (im, 0) when the frame does not allow it.
+    """
+    h, w = int(im.shape[0]), int(im.shape[1])
+    rs = int(im.stride(0))
+    off = int(im.storage_offset())
+    frame_w = rs // 3
+    x_byte = off % rs
+    if rs % 12 != 0 or x_byte % 3 != 0 or im.data_ptr() % 4 != (3 * (x_byte // 3)) % 4:
+        return im, 0
+    x = x_byte // 3
+    xa = x - x % 4
+    xe = -(-(x + w) // 4) * 4
+    if xe > frame_w:
+        return im, 0
+    view = im.as_strided((h, xe - xa, 3), (rs, 3, 1), off - 3 * (x - xa))
+    return view, x - xa
+
+
+def footprint_bytes(mtb, n: int, width: int, height: int, levels: int, host_staged: bool = False) -> int:
+    """Device bytes a stack request holds while in flight: its workspace, and for
+    a host-staged request the device copies of its n images in front of it."""
+    ws = int(mtb.mtb_stack_workspace_bytes(n, width, height, levels))
+    if ws <= 0:
+        raise ValueError("invalid stack request")
+    return ws + (n * staged_image_bytes(width, height) if host_staged else 0)
+
+
 def gpu_executor(pool_buffer, slots: int):
     """Executor and poll functions that run requests through libmtb on `slots` streams.
 
     pool_buffer is a uint8 device tensor holding the serving pool; request
-    workspaces are views into it.  Streams are created at default priority.
+    footprints are views into it.  A request whose images are CPU tensors is
+    host-staged: its footprint starts with one device image per input (see
+    footprint_bytes), filled by mtb_stage_rgb on the slot's stream, and the
+    workspace follows.  Streams are created at default priority.
     """
     import torch
 
@@ -201,12 +258,26 @@ def gpu_executor(pool_buffer, slots: int):
         s = streams[slot]
         # Inputs were produced on the current stream; the slot's stream waits for them.
         s.wait_stream(torch.cuda.current_stream(pool_buffer.device))
-        ws = pool_buffer[off:off + req.workspace_bytes]
-        n = len(req.images)
+        images = req.images
+        ws_off = off
+        if images[0].device.type == "cpu":
+            # The images of a stack share one row stride: every staged copy gets
+            # rows as long as the widest widened crop.
+            widened = [widen_for_dma(im) for im in req.images]
+            wmax = max(int(v.shape[1]) for v, _ in widened)
+            images = []
+            for im, (src, col) in zip(req.images, widened):
+                h, w = int(im.shape[0]), int(im.shape[1])
+                dst = pool_buffer[ws_off:ws_off + 3 * wmax * h].view(h, wmax, 3)
+                mtb.mtb_stage_rgb(src, dst[:, :int(src.shape[1])], stream=s)
+                images.append(dst[:, col:col + w])
+                ws_off += staged_image_bytes(w, h)
+        ws = pool_buffer[ws_off:off + req.workspace_bytes]
+        n = len(images)
         with torch.cuda.stream(s):
             shifts = torch.empty((n, 2), dtype=torch.int32, device=pool_buffer.device)
             errs = torch.empty(n, dtype=torch.int32, device=pool_buffer.device)
-            mtb.mtb_align_stack(req.images, req.levels, exclude_range=req.exclude_range,
+            mtb.mtb_align_stack(images, req.levels, exclude_range=req.exclude_range,
                                 ref_index=req.ref_index, workspace=ws, shifts=shifts, errs=errs,
                                 stream=s)
             ev = torch.cuda.Event()

@@ -268,6 +268,17 @@ def test_apply_shifts_validation(mtb):
     assert L.mtb_apply_shifts(*bad) == 1
 
 
+def test_stage_rgb_validation(mtb):
+    L = _c(mtb)
+    args = [FAKE, 192, 64, 48, FAKE, 256, NULL]
+    for i, v in ((0, NULL), (1, 191), (2, 0), (3, 0), (4, NULL), (5, 191)):
+        bad = list(args)
+        bad[i] = v
+        assert L.mtb_stage_rgb(*bad) == 1, (i, v)
+    # 2^16 x 2^16 pixels: strides valid, pixel count too large.
+    assert L.mtb_stage_rgb(FAKE, 3 << 16, 1 << 16, 1 << 16, FAKE, 3 << 16, NULL) == 1
+
+
 def test_quadrant_validation(mtb):
     L = _c(mtb)
     ws = L.mtb_quadrant_workspace_bytes(64, 48, 192, 3)

@@ -109,6 +109,22 @@ def test_bitmaps_exclusion_ranges(mtb, exclude):
         _check_pyramid(mtb, _to_dev(flat), flat, 3, exclude)
 
 
+@pytest.mark.parametrize("exclude", [0, 4, 10])
+def test_bitmaps_every_threshold_case(mtb, exclude):
+    """Medians on both sides of 128 for each of the three thresholds.
+
+    Gray images (equal channels give gray = channel) with values m + [-25, 25]
+    have medians near m; m runs from 0 to 255 in small steps so that every
+    ordering of max(m - X, 0), m + 1 and m + X + 1 against 128 and 256 occurs.
+    """
+    rng = np.random.default_rng(4242 + exclude)
+    for m in (0, 2, 40, 110, 115, 117, 118, 120, 122, 123, 124, 126, 127, 128, 130, 131,
+              132, 133, 137, 138, 139, 180, 244, 245, 250, 251, 254, 255):
+        v = np.clip(m + rng.integers(-25, 26, (97, 333)), 0, 255).astype(np.uint8)
+        img = np.repeat(v[:, :, None], 3, axis=2)
+        _check_pyramid(mtb, _to_dev(img), img, 3, exclude)
+
+
 def test_saturated_and_flat_images(mtb):
     for val in (0, 255, 128):
         img = np.full((150, 200, 3), val, np.uint8)

@@ -67,3 +67,52 @@ def test_served_results_equal_results_alone(mtb):
         got = results[r["rid"]]
         assert np.array_equal(got.shifts.cpu().numpy(), want["shifts"]), r["rid"]
         assert np.array_equal(got.errs.cpu().numpy().astype(np.int64), want["errs"]), r["rid"]
+
+
+def test_stage_rgb_copies_a_strided_host_view(mtb):
+    base = torch.from_numpy(np.random.default_rng(11).integers(0, 256, (70, 150, 3), dtype=np.uint8)).pin_memory()
+    view = base[5:65, 7:140]                       # rows 450 bytes apart, 133 pixels used
+    dst_buf = torch.full((60, 141, 3), 7, dtype=torch.uint8, device=DEV)
+    dst = dst_buf[:, :133]                         # device rows 423 bytes apart
+    mtb.mtb_stage_rgb(view, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(dst.cpu(), view)
+    assert bool((dst_buf[:, 133:] == 7).all())     # bytes past the row untouched
+
+
+@pytest.mark.timeout(600)
+def test_host_staged_serving_equals_device_staged(mtb):
+    from paper_2007_06483_amd.serving import Request, Server, footprint_bytes, gpu_executor
+
+    BW, BH = 1200, 800
+    base = synth.make_serve_base(BW, BH, 8, n_blobs=50)
+    base_host = [torch.from_numpy(b).pin_memory() for b in base]
+    base_dev = [torch.from_numpy(b).to(DEV) for b in base]
+    specs = synth.serve_requests(9, 300.0, 0.1, BW, BH, mp_range=(0.05, 0.4))
+    assert len(specs) >= 10
+
+    def requests(src, host):
+        return [Request(rid=r["rid"], arrival=0.0 if k < 6 else r["arrival"],
+                        images=[synth.serve_crop(src, r, i) for i in range(r["n"])], levels=r["levels"],
+                        workspace_bytes=footprint_bytes(mtb, r["n"], r["width"], r["height"], r["levels"], host))
+                for k, r in enumerate(specs)]
+
+    out = {}
+    for host in (False, True):
+        reqs = requests(base_host if host else base_dev, host)
+        slots = 3
+        pool_bytes = slots * max(q.workspace_bytes for q in reqs) + 4096
+        pool = torch.empty(pool_bytes, dtype=torch.uint8, device=DEV)
+        execute, poll = gpu_executor(pool, slots)
+        srv = Server(pool_bytes, slots, execute, poll)
+        out[host] = srv.run(reqs)
+        torch.cuda.synchronize()
+        assert srv.max_in_flight > 1
+    for a, b in zip(out[False], out[True]):
+        assert a.rid == b.rid
+        assert torch.equal(a.shifts, b.shifts), a.rid
+        assert torch.equal(a.errs, b.errs), a.rid
+    r = specs[len(specs) // 2]
+    host = [np.ascontiguousarray(synth.serve_crop(base, r, i)) for i in range(r["n"])]
+    want = oracle.align_stack(host, r["levels"], ref_index=r["n"] // 2, threads=4)
+    assert np.array_equal(out[True][r["rid"]].shifts.cpu().numpy(), want["shifts"])

@@ -103,3 +103,40 @@ def test_percentile_interpolates():
     assert percentile([1, 2, 3, 4], 50) == pytest.approx(2.5)
     assert percentile([5], 99) == 5
     assert percentile(list(range(101)), 99) == pytest.approx(99)
+
+
+def test_host_staged_footprint_holds_the_images_before_the_workspace():
+    import paper_2007_06483_amd as mtb
+    from paper_2007_06483_amd.serving import footprint_bytes, staged_image_bytes
+
+    assert staged_image_bytes(1, 1) == 256           # 7 pixels with the widening
+    assert staged_image_bytes(58, 4) == 768          # 3 * 64 * 4 bytes, already aligned
+    assert staged_image_bytes(59, 4) == 1024         # 780 bytes rounded up
+    n, w, h, L = 5, 1000, 700, 6
+    ws = mtb.mtb_stack_workspace_bytes(n, w, h, L)
+    assert footprint_bytes(mtb, n, w, h, L) == ws
+    assert footprint_bytes(mtb, n, w, h, L, host_staged=True) == ws + n * staged_image_bytes(w, h)
+    with pytest.raises(ValueError):
+        footprint_bytes(mtb, 0, w, h, L)
+
+
+def test_widen_for_dma_aligns_every_offset_and_keeps_the_crop():
+    import numpy as np
+    import torch
+
+    from paper_2007_06483_amd.serving import STAGE_WIDEN, widen_for_dma
+
+    frame = torch.from_numpy(np.random.default_rng(3).integers(0, 256, (40, 100, 3), dtype=np.uint8))
+    for x in range(0, 12):
+        for w in (1, 5, 17, 60, 100 - x):
+            crop = frame[7:30, x:x + w]
+            view, col = widen_for_dma(crop)
+            assert torch.equal(view[:, col:col + w], crop), (x, w)
+            ww = view.shape[1]
+            assert ww <= w + 2 * STAGE_WIDEN
+            assert view.stride(0) == 300 and (view.data_ptr() - frame.data_ptr()) % 4 == 0
+            assert (3 * ww) % 4 == 0 and view.data_ptr() % 4 == 0
+    # A frame whose rows are not a multiple of 4 bytes long is left alone.
+    odd = torch.zeros((10, 33, 3), dtype=torch.uint8)
+    v, col = widen_for_dma(odd[2:5, 3:9])
+    assert col == 0 and v.shape[1] == 6
