@@ -1135,7 +1135,15 @@ __host__ __device__ __forceinline__ int coarse_cw_log2(const LevelGeom &lv)
     return c;
 }
 
-__host__ __device__ __forceinline__ int coarse_slab_rows(const LevelGeom &lv) { return 8 * (256 >> coarse_cw_log2(lv)); }
+// Rows per stream of one coarse workgroup (all its loads are issued first).
+// Four rather than eight: twice the workgroups, each with half the serial
+// work, and more of them per compute unit to hide each other's latency.
+constexpr int kCoarseRows = 4;
+
+__host__ __device__ __forceinline__ int coarse_slab_rows(const LevelGeom &lv)
+{
+    return kCoarseRows * (256 >> coarse_cw_log2(lv));
+}
 
 __host__ __device__ __forceinline__ int coarse_slabs(const LevelGeom &lv)
 {
@@ -1179,7 +1187,7 @@ __device__ int2 coarse_walk(const SearchArgs &a, int p, const uint32_t *surf, bo
 __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
 {
     constexpr int kMaxR = 7;
-    constexpr int kRows = 8;  // rows per stream and slab, all loads issued first
+    constexpr int kRows = kCoarseRows;
     __shared__ uint32_t red[4][2 * kMaxR + 1];
     const int pair = blockIdx.y;
     const int wave = wave_id();
