@@ -381,7 +381,7 @@ def run_served(args, mtb, synth, torch, np, dev):
     main_run = serve(200.0, args.serve_seconds, 5)
     log(json.dumps(main_run))
     sweep = []
-    for rate in (800.0, 1600.0, 3200.0, 6400.0):
+    for rate in (800.0, 1600.0, 3200.0, 6400.0, 12800.0):
         sweep.append(serve(rate, 3.0, 50 + int(rate)))
         log(json.dumps(sweep[-1]))
     host_run, host_sweep = None, []

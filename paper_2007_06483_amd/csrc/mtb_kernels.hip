@@ -275,6 +275,32 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     gray4(d[rr][3 * k], d[rr][3 * k + 1], d[rr][3 * k + 2], &gv[rr][4 * k]);
+        } else if (full) {
+            // Rows at any byte alignment: the whole dwords overlapping the lane's
+            // 48 bytes (12, or 13 when the start is not 4-aligned; each holds a
+            // byte of the segment, so none reaches into a page the row does not
+            // touch), moved into place with v_alignbyte_b32.
+            uint32_t d[4][12];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const uint8_t *row = rgb + (int64_t)(y0 + rr) * a.stride + 3 * (int64_t)x0;
+                const uint32_t sh = (uint32_t)(uintptr_t)row & 3u;
+                const uint32_t *p = (const uint32_t *)((uintptr_t)row - sh);
+                uint32_t w[13];
+                const bool in = y0 + rr < g.H;
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    w[k] = in ? p[k] : 0u;
+                w[12] = in && sh ? p[12] : 0u;
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    d[rr][k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+            }
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    gray4(d[rr][3 * k], d[rr][3 * k + 1], d[rr][3 * k + 2], &gv[rr][4 * k]);
         } else {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {

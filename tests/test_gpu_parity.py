@@ -97,6 +97,14 @@ def test_pyramid_with_unaligned_rows(mtb, extra, offset):
     _check_pyramid(mtb, _strided_dev(img, extra, offset), img, 5)
 
 
+@pytest.mark.parametrize("extra,offset", [(0, 1), (0, 3), (2, 2), (7, 1), (9, 0), (13, 3)])
+def test_pyramid_unaligned_rows_several_tiles(mtb, extra, offset):
+    # Rows at every byte alignment (strides not a multiple of 4 give each row
+    # its own), over several 64 x 256 tiles with ragged right and bottom tiles.
+    img = _noise(200, 611, 7 + extra + offset)
+    _check_pyramid(mtb, _strided_dev(img, extra, offset), img, 7)
+
+
 @pytest.mark.parametrize("exclude", [0, 1, 7, 127, 200, 255])
 def test_bitmaps_exclusion_ranges(mtb, exclude):
     # Thresholds m + X + 1 above 255 and m - X below 0 (the band covers the whole range).
