@@ -235,13 +235,13 @@ mtb_status mtb_apply_shifts(const uint8_t *const *h_d_rgb, int32_t n, int32_t wi
                             uint8_t *const *h_d_out, int64_t out_stride, void *stream);
 
 /*
- * Host-staged input (Section III-B: the exposures are copied from host memory
- * to the GPU before the pyramids are built): enqueues on `stream` one 2-D
- * copy of an RGB image from host memory into device memory, row by row
- * (3 * width bytes of each of `height` rows).  With h_rgb in pinned memory
- * (hipHostMalloc) the copy is an asynchronous DMA that overlaps kernels on
- * other streams; with pageable memory it may return only once the copy is
- * done.  The host buffer must stay valid until the copy has run.  Not a step
+ * Host-staged input (Section II: every input image is copied to GPU memory
+ * once; Section IV: that host-to-device transfer is part of the measured
+ * time): enqueues on `stream` one 2-D copy of an RGB image from host memory
+ * into device memory (3 * width bytes of each of `height` rows).  With h_rgb
+ * in pinned memory (hipHostMalloc) the copy is an asynchronous DMA that
+ * overlaps kernels on other streams; with pageable memory it may return only
+ * once the copy is done.  The host buffer must stay valid until the copy has run.  Not a step
  * of the alignment: plumbing for callers whose frames arrive in host memory.
  * Speed: with h_rgb, d_rgb, both strides and 3 * width all multiples of 4 the
  * copy ran at 47-56 GB/s on MI355X over PCIe; a misaligned start address cut

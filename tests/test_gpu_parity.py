@@ -208,6 +208,14 @@ def test_align_stack_matches_oracle(mtb, n):
     _check_stack(mtb, imgs, 6)
 
 
+def test_align_stack_largest_stack(mtb):
+    # The largest stack the library takes (32 images), exposures repeating
+    # around the middle; every image against the middle reference.
+    n = mtb.MTB_MAX_STACK
+    imgs, _, _ = synth.make_stack(160, 96, n, 12, 31, 6, evs=[float(i % 7 - 3) for i in range(n)])
+    _check_stack(mtb, imgs, 4)
+
+
 def test_align_stack_reference_choice_and_exclusion(mtb):
     imgs, _, _ = synth.make_stack(256, 200, 4, 30, 77, 20)
     _check_stack(mtb, imgs, 5, ref_index=0)
