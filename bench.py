@@ -38,7 +38,10 @@ def log(*a):
 
 
 def level_sizes(lay):
-    return [(lay.level_width[l], lay.level_height[l], lay.words_per_row[l]) for l in range(lay.levels)]
+    """(W_l, H_l, words per row) of every level; words = ceil(W_l / 64), the method's
+    own count (the layout pads rows to an even number of words for the search)."""
+    return [(lay.level_width[l], lay.level_height[l], (lay.level_width[l] + 63) // 64)
+            for l in range(lay.levels)]
 
 
 def algorithmic_bytes(lay, n_images, n_pairs):
@@ -61,10 +64,6 @@ def algorithmic_bytes(lay, n_images, n_pairs):
     return per
 
 
-def kernel_search_bytes(lay, n_pairs, levels_in_launch):
-    return sum(n_pairs * 4 * 8 * lay.words_per_row[l] * lay.level_height[l] for l in levels_in_launch)
-
-
 def kernel_source_sha256():
     """Digest of the kernel sources, to tell whether stored counter figures are current."""
     h = hashlib.sha256()
@@ -74,14 +73,21 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def load_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if still current."""
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
+    taken on this kernel's launch in this workload and the kernel sources are unchanged.
+    (The chained and byte-map variants of a stack launch the same k_pyramid.)"""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel") != kernel or t.get("kernel_source_sha256") != kernel_source_sha256():
+    base = workload
+    for suffix in ("_chained", "_bytemaps"):
+        if kernel == "k_pyramid" and base.endswith(suffix):
+            base = base[: -len(suffix)]
+    if (t.get("kernel") != kernel or t.get("workload") != base
+            or t.get("kernel_source_sha256") != kernel_source_sha256()):
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -322,6 +328,73 @@ def run_apply(args, mtb, synth, torch, np, dev):
     print(json.dumps(result), flush=True)
 
 
+def run_quadrants(args, mtb, synth, torch, np, dev):
+    """The rotation check of the 7 x 6000x4000 stack: each of the six moving images
+    against the middle reference, both split into quadrants and every quadrant pair
+    aligned on its own (mtb_align_quadrants, six calls per step)."""
+    import oracle
+
+    log("generating stack7_6000x4000 ...")
+    w = synth.workload("stack7_6000x4000")
+    (imgs, _, ref), = w.stacks
+    n, W, H, L = len(imgs), w.width, w.height, w.levels
+    d = [torch.from_numpy(im).to(dev) for im in imgs]
+    movs = [k for k in range(n) if k != ref]
+    ws = torch.empty(mtb.mtb_quadrant_workspace_bytes(W, H, 3 * W, L), dtype=torch.uint8, device=dev)
+    mp_total = len(movs) * 2 * W * H / 1e6  # both images of every pair
+
+    def step():
+        return [mtb.mtb_align_quadrants(d[ref], d[k], L, workspace=ws) for k in movs]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mtb.mtb_profile_begin("k_pyramid")
+    t = time.perf_counter()
+    for i in range(args.steps):
+        mtb.mtb_profile_pause(i % args.event_every != 0)
+        out = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    launches, total_ms = mtb.mtb_profile_end()["k_pyramid"]
+    qw, qh = W // 2, H // 2
+    algo = 8 * pyramid_bytes(qw, qh, L)  # one launch: the four quadrants of both images
+    achieved = algo / (total_ms / launches / 1e3) / 1e9
+    got = [{k: v.cpu().numpy() for k, v in o.items()} for o in out]
+    result = {
+        "metric": METRIC, "value": round(mp_total / (ms / 1e3), 1), "unit": "MP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "quadrants7_6000x4000", "pairs": len(movs), "width": W, "height": H,
+                   "levels": L, "quadrant": f"{qw}x{qh}", "megapixels_per_step": round(mp_total, 3)},
+        "roofline": {"bound": "hbm", "kernel": "k_pyramid", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "avg_launch_us": round(total_ms / launches * 1e3, 2), "algorithmic_bytes_per_launch": algo},
+        "flags": [int(g["flag"][0]) for g in got],
+        "quadrant_shifts": [g["shifts"].tolist() for g in got],
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle ...")
+        same, reps, t = True, 0, time.perf_counter()
+        while True:
+            k = movs[reps % len(movs)]
+            want = oracle.align_quadrants(imgs[ref], imgs[k], L)
+            g = got[movs.index(k)]
+            same = same and bool(np.array_equal(g["shifts"], want["shifts"]) and
+                                 np.array_equal(g["errs"].astype(np.int64), want["errs"]) and
+                                 int(g["flag"][0]) == want["flag"])
+            reps += 1
+            dt = time.perf_counter() - t
+            if dt >= args.cpu_seconds and reps >= len(movs):
+                break
+        result["cpu_baseline"] = {"value": round(reps * 2 * W * H / 1e6 / dt, 3), "unit": "MP/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": f"{reps} quadrant checks of stack pairs ({2 * W * H / 1e6:.0f} MP each) "
+                                            f"in {dt:.2f} s, one thread"}
+        result["parity_vs_oracle"] = same
+    print(json.dumps(result), flush=True)
+
+
 def run_served(args, mtb, synth, torch, np, dev):
     """Poisson arrivals of exposure stacks served with continuous batching.
 
@@ -427,7 +500,7 @@ def main():
                     choices=["stack7_6000x4000", "stack7_6000x4000_chained", "stack7_6000x4000_bytemaps",
                              "pair_4096x3072", "pair_512x384",
                              "batch64_uneven",
-                             "served_poisson200", "apply7_6000x4000"])
+                             "served_poisson200", "apply7_6000x4000", "quadrants7_6000x4000"])
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
     ap.add_argument("--serve-slots", type=int, default=4, help="served mode: stacks in flight at most")
     ap.add_argument("--serve-host-seconds", type=float, default=20.0,
@@ -467,6 +540,8 @@ def main():
         return run_served(args, mtb, synth, torch, np, dev)
     if args.workload == "apply7_6000x4000":
         return run_apply(args, mtb, synth, torch, np, dev)
+    if args.workload == "quadrants7_6000x4000":
+        return run_quadrants(args, mtb, synth, torch, np, dev)
 
     log(f"generating {args.workload} ...")
     t0 = time.perf_counter()
@@ -547,7 +622,7 @@ def main():
         "peak": PEAK_HBM_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBPS, 4),
-        "traffic": load_traffic(dominant),
+        "traffic": load_traffic(dominant, args.workload),
         "avg_launch_us": round(avg_s * 1e6, 2),
         "evented_launches": launches,
         "algorithmic_bytes_per_launch": algo[dominant],

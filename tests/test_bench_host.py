@@ -1,0 +1,56 @@
+"""Host logic of bench.py: the one-GPU guard, the algorithmic byte model and the
+rule that stored counter figures apply only to the launch they were taken on."""
+
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_algorithmic_bytes_of_the_stack_workload():
+    import paper_2007_06483_amd as mtb
+
+    W, H, L, n = 6000, 4000, 7, 7
+    lay = mtb.mtb_get_layout(W, H, L)
+    per = bench.algorithmic_bytes(lay, n, n - 1)
+    gray = sum((W >> l) * (H >> l) for l in range(L))
+    maps = sum(8 * (((W >> l) + 63) // 64) * (H >> l) for l in range(L))
+    assert per["k_pyramid"] == n * (3 * W * H + gray) == 727985237
+    assert per["k_bitmaps"] == n * (gray + 2 * maps)
+    assert per["search"] == (n - 1) * 4 * maps
+    assert per["step"] == per["k_pyramid"] + per["k_bitmaps"] + per["search"]
+    assert bench.pyramid_bytes(W, H, L) * n == per["k_pyramid"]
+
+
+def test_stored_traffic_applies_only_to_its_own_launch(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"kernel": "k_pyramid", "workload": "stack7_6000x4000",
+                             "kernel_source_sha256": bench.kernel_source_sha256(),
+                             "traffic_bytes_per_launch": 123}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.load_traffic("k_pyramid", "stack7_6000x4000") == 123
+    assert bench.load_traffic("k_pyramid", "stack7_6000x4000_chained") == 123   # same k_pyramid launch
+    assert bench.load_traffic("k_pyramid", "stack7_6000x4000_bytemaps") == 123
+    assert bench.load_traffic("k_pyramid", "pair_4096x3072") is None
+    assert bench.load_traffic("k_pyramid", "quadrants7_6000x4000") is None
+    assert bench.load_traffic("k_bitmaps", "stack7_6000x4000") is None
+    f.write_text(json.dumps({"kernel": "k_pyramid", "workload": "stack7_6000x4000",
+                             "kernel_source_sha256": "0" * 64, "traffic_bytes_per_launch": 123}))
+    assert bench.load_traffic("k_pyramid", "stack7_6000x4000") is None       # kernels changed since
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
+    assert bench.load_traffic("k_pyramid", "stack7_6000x4000") is None
