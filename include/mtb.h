@@ -215,6 +215,57 @@ mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int
                                    uint32_t *d_trace, void *stream);
 
 /*
+ * Launch shapes and their tuner.  How a stack alignment is cut into
+ * workgroups never changes its results (every shape gives the same bits);
+ * it changes its speed, and the best shape depends on the image size and
+ * count.  A shape: k_pyramid and k_bitmaps workgroups as a percentage of one
+ * round of the workgroups the device holds at once, and the rows each row
+ * stream of k_search_fine covers at every level (0: the built-in rule, the
+ * fewest rows that keep one level's grid within one resident round).
+ * Shapes are kept per (n, width, height, levels, row_stride mod 16 class) in
+ * a process-wide table guarded by a mutex; mtb_align_stack and
+ * mtb_align_stack_chained use the table's shape for their key, the built-in
+ * shape otherwise.
+ */
+typedef struct mtb_launch_shape {
+    int32_t pyramid_slots_pct;  /* 25 .. 400 (default 100) */
+    int32_t bitmaps_blocks_pct; /* 25 .. 100 (default 100) */
+    int32_t search_rows[16];    /* per level: 0, or a multiple of 4 in 4 .. 64 */
+    float step_ms;              /* mtb_tune_stack: median time of one call with this shape */
+    float default_ms;           /* mtb_tune_stack: the same with the built-in shape */
+} mtb_launch_shape;
+
+/*
+ * Tunes the launch shape of mtb_align_stack for these images: times whole
+ * alignments (median of 7 after a warm-up, HIP events on `stream`) under the
+ * built-in shape and under candidates changed one knob at a time (pyramid
+ * 50/75/150/200 %, bitmaps 50/75 %, each fine level's rows halved or
+ * doubled), keeps a change only if it is at least 2 % faster, stores the
+ * result in the table and writes it to *h_out.  Arguments as for
+ * mtb_align_stack; d_shifts and d_errs hold the alignment's results when it
+ * returns.  Waits for the device (not capturable in a HIP graph); allocates
+ * no device memory.
+ * Errors: as mtb_align_stack; MTB_ERR_INVALID_ARG for a null h_out.
+ */
+mtb_status mtb_tune_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
+                          int64_t row_stride, int32_t levels, int32_t exclude_range, int32_t ref_index,
+                          void *d_workspace, size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                          void *stream, mtb_launch_shape *h_out);
+
+/* Stores *shape for the key (e.g. a shape tuned in an earlier run).
+ * Errors: MTB_ERR_INVALID_ARG (null shape, a field out of range, invalid sizes). */
+mtb_status mtb_set_shape(int32_t n, int32_t width, int32_t height, int64_t row_stride, int32_t levels,
+                         const mtb_launch_shape *shape);
+
+/* The stored shape for the key into *h_out.
+ * Errors: MTB_ERR_INVALID_ARG (null h_out, or no shape stored for the key). */
+mtb_status mtb_tuned_shape(int32_t n, int32_t width, int32_t height, int64_t row_stride, int32_t levels,
+                           mtb_launch_shape *h_out);
+
+/* Forgets every stored shape. */
+void mtb_tune_reset(void);
+
+/*
  * Translates every image of a stack by its shift (Section III-B: the shift
  * found for an exposure is applied to it, bringing it onto the reference):
  *   out_i[y][x] = in_i[y - dy_i][x - dx_i]   (all three channels)

@@ -40,6 +40,10 @@ __all__ = [
     "mtb_stack_bytemaps_workspace_bytes",
     "mtb_apply_shifts",
     "mtb_stage_rgb",
+    "mtb_tune_stack",
+    "mtb_set_shape",
+    "mtb_tuned_shape",
+    "mtb_tune_reset",
     "mtb_quadrant_workspace_bytes",
     "mtb_align_quadrants",
     "MTB_FILL_ZERO",
@@ -102,6 +106,23 @@ class _BatchItem(ctypes.Structure):
 
 class _KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+class _LaunchShape(ctypes.Structure):
+    _fields_ = [("pyramid_slots_pct", ctypes.c_int32), ("bitmaps_blocks_pct", ctypes.c_int32),
+                ("search_rows", ctypes.c_int32 * MTB_MAX_LEVELS), ("step_ms", ctypes.c_float),
+                ("default_ms", ctypes.c_float)]
+
+
+def _shape_dict(c: _LaunchShape) -> dict:
+    return {"pyramid_slots_pct": c.pyramid_slots_pct, "bitmaps_blocks_pct": c.bitmaps_blocks_pct,
+            "search_rows": list(c.search_rows), "step_ms": float(c.step_ms), "default_ms": float(c.default_ms)}
+
+
+def _shape_struct(d: dict) -> _LaunchShape:
+    rows = list(d.get("search_rows", [])) + [0] * MTB_MAX_LEVELS
+    return _LaunchShape(int(d.get("pyramid_slots_pct", 100)), int(d.get("bitmaps_blocks_pct", 100)),
+                        (ctypes.c_int32 * MTB_MAX_LEVELS)(*rows[:MTB_MAX_LEVELS]), 0.0, 0.0)
 
 
 class Layout:
@@ -169,6 +190,15 @@ def lib():
     L.mtb_align_quadrants.restype = ctypes.c_int
     L.mtb_apply_shifts.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, P, i32, ctypes.POINTER(P), i64, P]
     L.mtb_apply_shifts.restype = ctypes.c_int
+    L.mtb_tune_stack.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, i32, i32, P, sz, P, P, P,
+                                 ctypes.POINTER(_LaunchShape)]
+    L.mtb_tune_stack.restype = ctypes.c_int
+    L.mtb_set_shape.argtypes = [i32, i32, i32, i64, i32, ctypes.POINTER(_LaunchShape)]
+    L.mtb_set_shape.restype = ctypes.c_int
+    L.mtb_tuned_shape.argtypes = [i32, i32, i32, i64, i32, ctypes.POINTER(_LaunchShape)]
+    L.mtb_tuned_shape.restype = ctypes.c_int
+    L.mtb_tune_reset.argtypes = []
+    L.mtb_tune_reset.restype = None
     L.mtb_stage_rgb.argtypes = [P, i64, i32, i32, P, i64, P]
     L.mtb_stage_rgb.restype = ctypes.c_int
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
@@ -355,6 +385,51 @@ def mtb_align_stack(images, levels: int, exclude_range: int = 4, ref_index: int 
                                   _ptr(workspace), workspace.numel(), _ptr(shifts), _ptr(errs),
                                   _ptr(tr), _stream(stream)))
     return {"shifts": shifts, "errs": errs, "trace": tr, "workspace": workspace}
+
+
+def mtb_tune_stack(images, levels: int, exclude_range: int = 4, ref_index: int = -1,
+                   workspace: torch.Tensor | None = None, shifts=None, errs=None, stream=None) -> dict:
+    """Tune and store the launch shape of mtb_align_stack for this stack (see mtb.h).
+
+    Returns the chosen shape as a dict (with step_ms and default_ms); the
+    stack's shifts and errors are left in ``shifts`` / ``errs`` if given.
+    """
+    n = len(images)
+    if not 1 <= n <= MTB_MAX_STACK:
+        raise ValueError(f"a stack holds 1..{MTB_MAX_STACK} images")
+    W, H, stride = _rgb_geometry(images[0])
+    for im in images:
+        if _rgb_geometry(im) != (W, H, stride) or im.device != images[0].device:
+            raise ValueError("all images of a stack must share size, stride and device")
+    dev = images[0].device
+    workspace = _buffer(max(mtb_stack_workspace_bytes(n, W, H, levels), 1), dev, workspace)
+    if shifts is None:
+        shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    if errs is None:
+        errs = torch.empty(n, dtype=torch.int32, device=dev)
+    ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in images])
+    out = _LaunchShape()
+    _check("mtb_tune_stack",
+           lib().mtb_tune_stack(ptrs, n, W, H, stride, levels, exclude_range, ref_index, _ptr(workspace),
+                                workspace.numel(), _ptr(shifts), _ptr(errs), _stream(stream), ctypes.byref(out)))
+    return _shape_dict(out)
+
+
+def mtb_set_shape(n: int, width: int, height: int, row_stride: int, levels: int, shape: dict) -> None:
+    c = _shape_struct(shape)
+    _check("mtb_set_shape", lib().mtb_set_shape(n, width, height, row_stride, levels, ctypes.byref(c)))
+
+
+def mtb_tuned_shape(n: int, width: int, height: int, row_stride: int, levels: int):
+    """The stored shape for the key, or None."""
+    c = _LaunchShape()
+    if lib().mtb_tuned_shape(n, width, height, row_stride, levels, ctypes.byref(c)) != MTB_OK:
+        return None
+    return _shape_dict(c)
+
+
+def mtb_tune_reset() -> None:
+    lib().mtb_tune_reset()
 
 
 def mtb_apply_shifts(images, shifts: torch.Tensor, fill: int = MTB_FILL_ZERO, out=None,

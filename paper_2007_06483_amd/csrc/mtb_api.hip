@@ -2,6 +2,8 @@
 // layout, and the launch sequence of each call.  No device memory is
 // allocated here; every buffer comes from the caller.
 
+#include <algorithm>
+#include <map>
 #include <mutex>
 #include <string.h>
 #include <vector>
@@ -148,7 +150,7 @@ int64_t set_workspace_bytes(const Geometry &g, int n, int npairs, bool bytemaps 
 // regions to clear first (taken by value, its free slots are used here).
 hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int align, int exclude,
                        uint8_t *ws, SearchOutputs out, ZeroArgs zero, int cus, hipStream_t s,
-                       bool bytemaps = false)
+                       bool bytemaps = false, const LaunchTune &t = LaunchTune())
 {
     const int n = ps.n, npairs = ps.npairs;
     const int64_t mb = bytemaps ? g.bytemaps_bytes : g.bitmaps_bytes;  // maps buffer per image
@@ -177,7 +179,7 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     pa.n = n;
     pa.align = align;
     pa.g = g;
-    e = launch_pyramid(pa, cus, s);
+    e = launch_pyramid(pa, cus, s, t.pyr_pct);
     if (e != hipSuccess)
         return e;
 
@@ -191,7 +193,7 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     ba.exclude = exclude;
     ba.g = g;
     fill_chunk_starts(g, ba.chunk_start);
-    e = bytemaps ? launch_bytemaps(ba, cus, s) : launch_bitmaps(ba, cus, s);
+    e = bytemaps ? launch_bytemaps(ba, cus, s) : launch_bitmaps(ba, cus, s, t.bm_pct);
     if (e != hipSuccess || npairs == 0)
         return e;
 
@@ -208,7 +210,73 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     sa.npairs = npairs;
     sa.out = out;
     sa.g = g;
-    return bytemaps ? launch_search_bytes(sa, cus, s) : launch_search(sa, cus, s);
+    return bytemaps ? launch_search_bytes(sa, cus, s) : launch_search(sa, cus, s, t.rows);
+}
+
+// Tuned launch shapes of stack alignments, per (images, size, levels, row
+// alignment); filled by mtb_tune_stack / mtb_set_shape, read by align_stack.
+struct TuneKey {
+    int n, w, h, levels, align;
+    bool operator<(const TuneKey &o) const
+    {
+        return n != o.n ? n < o.n : w != o.w ? w < o.w : h != o.h ? h < o.h : levels != o.levels ? levels < o.levels
+                                                                                                  : align < o.align;
+    }
+};
+std::mutex g_tune_mutex;
+std::map<TuneKey, LaunchTune> g_tune_table;
+
+bool tune_lookup(const TuneKey &k, LaunchTune *t)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    const auto it = g_tune_table.find(k);
+    if (it == g_tune_table.end())
+        return false;
+    *t = it->second;
+    return true;
+}
+
+void tune_store(const TuneKey &k, const LaunchTune &t)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_table[k] = t;
+}
+
+TuneKey tune_key(int n, int w, int h, int levels, int64_t stride)
+{
+    return TuneKey{n, w, h, levels, stride % 16 == 0 ? 16 : (stride % 4 == 0 ? 4 : 1)};
+}
+
+bool shape_valid(const mtb_launch_shape &s)
+{
+    if (s.pyramid_slots_pct < 25 || s.pyramid_slots_pct > 400 || s.bitmaps_blocks_pct < 25 ||
+        s.bitmaps_blocks_pct > 100)
+        return false;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        const int r = s.search_rows[l];
+        if (r != 0 && (r < kRowsStep || r > kRowsMax || r % kRowsStep != 0))
+            return false;
+    }
+    return true;
+}
+
+LaunchTune from_shape(const mtb_launch_shape &s)
+{
+    LaunchTune t;
+    t.pyr_pct = s.pyramid_slots_pct;
+    t.bm_pct = s.bitmaps_blocks_pct;
+    for (int l = 0; l < kMaxLevels; ++l)
+        t.rows[l] = s.search_rows[l];
+    return t;
+}
+
+void to_shape(const LaunchTune &t, mtb_launch_shape *s)
+{
+    memset(s, 0, sizeof(*s));
+    s->pyramid_slots_pct = t.pyr_pct;
+    s->bitmaps_blocks_pct = t.bm_pct;
+    for (int l = 0; l < kMaxLevels; ++l)
+        s->search_rows[l] = t.rows[l];
 }
 
 // Items of a batch that share one launch set: same geometry and stride, at
@@ -469,7 +537,8 @@ namespace {
 mtb_status align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
                        int64_t row_stride, int32_t levels, int32_t exclude_range, int32_t ref_index,
                        void *d_workspace, size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
-                       uint32_t *d_trace, bool chained, hipStream_t s, bool bytemaps = false)
+                       uint32_t *d_trace, bool chained, hipStream_t s, bool bytemaps = false,
+                       const LaunchTune *shape = nullptr)
 {
     Geometry g;
     if (!h_d_rgb || n < 1 || n > kMaxStack || !d_workspace || !d_shifts || !d_errs ||
@@ -523,7 +592,12 @@ mtb_status align_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, 
         z.words[z.count++] = 9 * (int64_t)levels * n;
     }
     uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
-    hipError_t e = enqueue_set(ps, g, row_stride, align, exclude_range, ws, out, z, cus, s, bytemaps);
+    LaunchTune t;
+    if (shape)
+        t = *shape;
+    else if (!bytemaps)
+        tune_lookup(tune_key(n, width, height, levels, row_stride), &t);
+    hipError_t e = enqueue_set(ps, g, row_stride, align, exclude_range, ws, out, z, cus, s, bytemaps, t);
     if (e == hipSuccess && chained && n > 1)
         e = launch_chain(d_shifts, n, ref, s);
     return device_status(e);
@@ -569,6 +643,125 @@ mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int
 {
     return align_stack(h_d_rgb, n, width, height, row_stride, levels, exclude_range, ref_index, d_workspace,
                        workspace_bytes, d_shifts, d_errs, d_trace, true, (hipStream_t)stream);
+}
+
+mtb_status mtb_tune_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
+                          int64_t row_stride, int32_t levels, int32_t exclude_range, int32_t ref_index,
+                          void *d_workspace, size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                          void *stream, mtb_launch_shape *h_out)
+{
+    if (!h_out)
+        return MTB_ERR_INVALID_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    auto run = [&](const LaunchTune &t) {
+        return align_stack(h_d_rgb, n, width, height, row_stride, levels, exclude_range, ref_index, d_workspace,
+                           workspace_bytes, d_shifts, d_errs, nullptr, false, s, false, &t);
+    };
+    LaunchTune best;
+    mtb_status st = run(best);  // validates every argument before anything is timed
+    if (st != MTB_OK)
+        return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        return MTB_ERR_DEVICE;
+    }
+    constexpr int kReps = 7;
+    // Median event time of kReps calls with shape t, after one warm-up call.
+    auto time = [&](const LaunchTune &t, float *ms) -> mtb_status {
+        mtb_status r = run(t);
+        float v[kReps];
+        for (int k = 0; k < kReps && r == MTB_OK; ++k) {
+            if (hipEventRecord(e0, s) != hipSuccess)
+                return MTB_ERR_DEVICE;
+            r = run(t);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&v[k], e0, e1) != hipSuccess)
+                return MTB_ERR_DEVICE;
+        }
+        if (r != MTB_OK)
+            return r;
+        std::sort(v, v + kReps);
+        *ms = v[kReps / 2];
+        return MTB_OK;
+    };
+    float best_ms = 0.f, default_ms = 0.f;
+    st = time(best, &best_ms);
+    default_ms = best_ms;
+    auto consider = [&](const LaunchTune &cand) {
+        float ms = 0.f;
+        if (st == MTB_OK)
+            st = time(cand, &ms);
+        if (st == MTB_OK && ms < 0.98f * best_ms) {
+            best = cand;
+            best_ms = ms;
+        }
+    };
+    for (int pct : {50, 75, 150, 200}) {
+        LaunchTune c = best;
+        c.pyr_pct = pct;
+        consider(c);
+    }
+    for (int pct : {50, 75}) {
+        LaunchTune c = best;
+        c.bm_pct = pct;
+        consider(c);
+    }
+    Geometry g;
+    make_geometry(width, height, levels, &g);  // valid: the first run checked it
+    const int cus = current_device_cus();
+    const int npairs = n - 1;
+    for (int l = levels - 1 - coarse_level_count(g); l >= 0 && npairs > 0; --l) {
+        const int r0 = search_rows_rule(g, l, npairs, cus);
+        for (int r : {r0 / 2, 2 * r0}) {
+            if (r < kRowsStep || r > kRowsMax || r % kRowsStep != 0)
+                continue;
+            LaunchTune c = best;
+            c.rows[l] = r;
+            consider(c);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MTB_OK)
+        return st;
+    // The winning shape leaves its results in d_shifts / d_errs as well.
+    st = run(best);
+    if (st != MTB_OK)
+        return st;
+    tune_store(tune_key(n, width, height, levels, row_stride), best);
+    to_shape(best, h_out);
+    h_out->step_ms = best_ms;
+    h_out->default_ms = default_ms;
+    return MTB_OK;
+}
+
+mtb_status mtb_set_shape(int32_t n, int32_t width, int32_t height, int64_t row_stride, int32_t levels,
+                         const mtb_launch_shape *shape)
+{
+    Geometry g;
+    if (!shape || n < 1 || n > kMaxStack || row_stride < 3 * (int64_t)width || !make_geometry(width, height, levels, &g) ||
+        !shape_valid(*shape))
+        return MTB_ERR_INVALID_ARG;
+    tune_store(tune_key(n, width, height, levels, row_stride), from_shape(*shape));
+    return MTB_OK;
+}
+
+mtb_status mtb_tuned_shape(int32_t n, int32_t width, int32_t height, int64_t row_stride, int32_t levels,
+                           mtb_launch_shape *h_out)
+{
+    LaunchTune t;
+    if (!h_out || !tune_lookup(tune_key(n, width, height, levels, row_stride), &t))
+        return MTB_ERR_INVALID_ARG;
+    to_shape(t, h_out);
+    return MTB_OK;
+}
+
+void mtb_tune_reset(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_table.clear();
 }
 
 mtb_status mtb_apply_shifts(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,

@@ -176,10 +176,22 @@ hipError_t launch_kernel(const char *name, void (*k)(A), dim3 grid, dim3 block, 
     return e;
 }
 
+// Launch shapes a tuner may change (results never depend on them): k_pyramid
+// and k_bitmaps workgroups as a percentage of one round of resident
+// workgroups, and k_search_fine rows per stream per level (0: the rule that
+// keeps the grid within one resident round).
+constexpr int kRowsStep = 4;   // rows per stream come in multiples of this
+constexpr int kRowsMax = 64;
+struct LaunchTune {
+    int32_t pyr_pct = 100;
+    int32_t bm_pct = 100;
+    int32_t rows[kMaxLevels] = {};
+};
+
 // Launch helpers (mtb_kernels.hip).  Each returns the hipError_t of its launches.
 hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);
-hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s);
-hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s);
+hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s, int slots_pct = 100);
+hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s, int blocks_pct = 100);
 hipError_t launch_apply(const ApplyArgs &a, int device_cus, hipStream_t s);
 // The byte-map comparison path: T/E as 255/0 bytes, and the search over them.
 hipError_t launch_bytemaps(const BitmapArgs &a, int device_cus, hipStream_t s);
@@ -191,6 +203,13 @@ hipError_t launch_chain(int32_t *d_shifts, int n, int ref, hipStream_t s);
 hipError_t launch_quadrant_flag(const int32_t *d_shifts, int32_t tol, int32_t *d_flag, hipStream_t s);
 // Searches every level of every pair and writes a.out; a.state and *a.done
 // must be zero.
-hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s);
+// Levels L-1 .. L-coarse_level_count(g) are searched exhaustively; the others
+// are the fine levels.
+int coarse_level_count(const Geometry &g);
+// Rows per stream launch_search uses at fine level l without a tuned value.
+int search_rows_rule(const Geometry &g, int l, int npairs, int device_cus);
+int search_row_blocks(const Geometry &g, int l, int rows);
+// rows: per-level rows per stream (LaunchTune::rows), or null for the rule.
+hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s, const int32_t *rows = nullptr);
 
 }  // namespace mtb

@@ -1694,16 +1694,16 @@ hipError_t launch_zero(const ZeroArgs &a, hipStream_t s)
     return launch_kernel("k_zero", k_zero, dim3(blocks, a.count), dim3(256), s, a);
 }
 
-hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s)
+hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s, int slots_pct)
 {
     PyramidArgs a = in;
     a.tiles_x = (a.g.W + kTileW - 1) / kTileW;
     a.tiles_y = (a.g.H + kTileH - 1) / kTileH;
     const int64_t total = (int64_t)a.tiles_x * a.tiles_y * a.n;
-    // One round of resident workgroups; each XCD gets the same number of
-    // slots (see k_pyramid).
+    // One round of resident workgroups (scaled by slots_pct); each XCD gets
+    // the same number of slots (see k_pyramid).
     const int64_t share = (total + kXcds - 1) / kXcds;
-    int64_t slots = (int64_t)cus * resident_per_cu(k_pyramid) / kXcds;
+    int64_t slots = (int64_t)cus * resident_per_cu(k_pyramid) * slots_pct / (100 * kXcds);
     slots = slots > share ? share : (slots < 1 ? 1 : slots);
     a.xcd_tiles = (int32_t)share;
     const int blocks = (int)(slots * kXcds);
@@ -1772,11 +1772,11 @@ hipError_t launch_search_bytes(SearchArgs a, int cus, hipStream_t s)
     return hipSuccess;
 }
 
-hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
+hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s, int blocks_pct)
 {
     const int64_t total = a.chunk_start[a.g.L] * a.n;
     int64_t blocks = (total + 3) / 4;
-    const int64_t cap = (int64_t)cus * resident_per_cu(k_bitmaps);
+    const int64_t cap = (int64_t)cus * resident_per_cu(k_bitmaps) * blocks_pct / 100;
     blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
     return launch_kernel("k_bitmaps", k_bitmaps, dim3((unsigned)blocks), dim3(256), s, a);
 }
@@ -1785,12 +1785,41 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s)
 // its window rows stay cheap for one workgroup: at most this many dwords.
 constexpr int64_t kCoarseDwords = 8192;
 
-hipError_t launch_search(SearchArgs a, int cus, hipStream_t s)
+int coarse_level_count(const Geometry &g)
 {
-    const Geometry &g = a.g;
     int cn = 0;
     while (cn < kCoarseLevels && cn < g.L && (int64_t)2 * g.lv[g.L - 1 - cn].wpr * g.lv[g.L - 1 - cn].h <= kCoarseDwords)
         ++cn;
+    return cn;
+}
+
+// Workgroups per pair of one fine level.  Workgroups are dealt to the XCDs
+// in turn, so with a row of blocks whose length is a multiple of kXcds every
+// pair's workgroup for one unit runs on the same XCD, whose L2 then serves
+// the shared reference rows.
+int search_row_blocks(const Geometry &g, int l, int rows)
+{
+    return ((plan_level(g.lv[l], rows).units + 3) / 4 + kXcds - 1) / kXcds * kXcds;
+}
+
+int search_rows_rule(const Geometry &g, int l, int npairs, int cus)
+{
+    // Rows per stream: the fewest (a multiple of the batches in flight) that
+    // keep the grid within one round of resident workgroups, so that every
+    // compute unit holds about as many workgroups as it can run and none
+    // waits for another to finish.
+    static_assert(kRowsStep == kSearchBatch * kSearchDepth, "rows per stream fill whole batches");
+    const int64_t resident = (int64_t)cus * resident_per_cu(k_search_fine);
+    int rows = kRowsStep;
+    while (rows < kRowsMax && (int64_t)search_row_blocks(g, l, rows) * npairs > resident)
+        rows += kRowsStep;
+    return rows;
+}
+
+hipError_t launch_search(SearchArgs a, int cus, hipStream_t s, const int32_t *tuned_rows)
+{
+    const Geometry &g = a.g;
+    const int cn = coarse_level_count(g);
     a.coarse_n = cn;
     hipError_t e = hipSuccess;
     if (cn > 0) {
@@ -1801,26 +1830,12 @@ hipError_t launch_search(SearchArgs a, int cus, hipStream_t s)
         if (e != hipSuccess)
             return e;
     }
-    // Workgroups are dealt to the XCDs in turn, so with a row of blocks whose
-    // length is a multiple of kXcds every pair's workgroup for one unit runs
-    // on the same XCD, whose L2 then serves the shared reference rows.
-    auto row_blocks = [&](int l, int rows) {
-        return ((plan_level(g.lv[l], rows).units + 3) / 4 + kXcds - 1) / kXcds * kXcds;
-    };
-    const int64_t resident = (int64_t)cus * resident_per_cu(k_search_fine);
     for (int l = g.L - 1 - cn; l >= 0; --l) {
-        // Rows per stream: the fewest (a multiple of the batches in flight)
-        // that keep the grid within one round of resident workgroups, so that
-        // every compute unit holds about as many workgroups as it can run and
-        // none waits for another to finish.
-        constexpr int kStep = kSearchBatch * kSearchDepth;
-        int rows = kStep;
-        while (rows < 64 && (int64_t)row_blocks(l, rows) * a.npairs > resident)
-            rows += kStep;
+        const int rows = tuned_rows && tuned_rows[l] > 0 ? tuned_rows[l] : search_rows_rule(g, l, a.npairs, cus);
         a.level = l;
         a.rows_per_stream = rows;
-        const int blocks = row_blocks(l, rows);
-        e = launch_kernel("k_search_fine", k_search_fine, dim3(blocks, a.npairs), dim3(256), s, a);
+        e = launch_kernel("k_search_fine", k_search_fine, dim3(search_row_blocks(g, l, rows), a.npairs), dim3(256),
+                          s, a);
         if (e != hipSuccess)
             return e;
     }
