@@ -506,7 +506,8 @@ def main():
     ap.add_argument("--serve-host-seconds", type=float, default=20.0,
                     help="served mode: length of the host-staged run (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shape")
+    ap.add_argument("--tune", action="store_true",
+                    help="let mtb_tune_stack pick the launch shape before timing (default: built-in shape)")
     ap.add_argument("--event-every", type=int, default=4,
                     help="time the dominant kernel with HIP events in every N-th timed step")
     ap.add_argument("--cpu-threads", type=int, default=16)
@@ -571,10 +572,12 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # Launch shape: the library's tuner picks it once, before timing (the
-    # byte-map path has no tunable shape); every shape gives the same results.
+    # Launch shape: with --tune the library's tuner picks it once, before
+    # timing (the byte-map path has no tunable shape); every shape gives the
+    # same results.  Without it the built-in shape runs, as in the committed
+    # rocprofv3 summaries (the tuner's trial launches would mix into them).
     shape = None
-    if not bytemaps and not args.no_tune:
+    if not bytemaps and args.tune:
         shape = mtb.mtb_tune_stack(d_imgs, L, ref_index=ref, workspace=ws, shifts=shifts, errs=errs)
         log(f"launch shape: {json.dumps(shape)}")
     torch.cuda.synchronize()
@@ -690,7 +693,8 @@ def main():
         "step_us": {"median": round(step_us[len(step_us) // 2], 1), "min": round(step_us[0], 1),
                     "max": round(step_us[-1], 1), "steps": len(step_us)},
         "e2e_incl_h2d": {"ms_per_step": round(e2e_ms, 3), "MPps": round(mp_total / (e2e_ms / 1e3), 1)},
-        "launch_shape": None if shape is None else {
+        "launch_shape": {"tuned": False, "pyramid_slots_pct": 100, "bitmaps_blocks_pct": 100,
+                         "search_rows": "built-in rule"} if shape is None else {
             "tuned": True, "pyramid_slots_pct": shape["pyramid_slots_pct"],
             "bitmaps_blocks_pct": shape["bitmaps_blocks_pct"], "search_rows": shape["search_rows"][:L],
             "tuner_step_ms": round(shape["step_ms"], 4), "tuner_default_ms": round(shape["default_ms"], 4)},
