@@ -266,6 +266,15 @@ mtb_status mtb_tuned_shape(int32_t n, int32_t width, int32_t height, int64_t row
 void mtb_tune_reset(void);
 
 /*
+ * For tests of error handling (callers that must survive a failed launch):
+ * after `after` further kernel launches from the calling thread succeed, the
+ * next one returns its failure without being issued, once, so the library
+ * call that made it returns MTB_ERR_DEVICE; `after` < 0 cancels.  Nothing
+ * faults on the device: the failing kernel is never launched.
+ */
+mtb_status mtb_test_fail_launch(int32_t after);
+
+/*
  * Translates every image of a stack by its shift (Section III-B: the shift
  * found for an exposure is applied to it, bringing it onto the reference):
  *   out_i[y][x] = in_i[y - dy_i][x - dx_i]   (all three channels)

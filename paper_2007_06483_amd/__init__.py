@@ -44,6 +44,7 @@ __all__ = [
     "mtb_set_shape",
     "mtb_tuned_shape",
     "mtb_tune_reset",
+    "mtb_test_fail_launch",
     "mtb_quadrant_workspace_bytes",
     "mtb_align_quadrants",
     "MTB_FILL_ZERO",
@@ -199,6 +200,8 @@ def lib():
     L.mtb_tuned_shape.restype = ctypes.c_int
     L.mtb_tune_reset.argtypes = []
     L.mtb_tune_reset.restype = None
+    L.mtb_test_fail_launch.argtypes = [i32]
+    L.mtb_test_fail_launch.restype = ctypes.c_int
     L.mtb_stage_rgb.argtypes = [P, i64, i32, i32, P, i64, P]
     L.mtb_stage_rgb.restype = ctypes.c_int
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
@@ -430,6 +433,11 @@ def mtb_tuned_shape(n: int, width: int, height: int, row_stride: int, levels: in
 
 def mtb_tune_reset() -> None:
     lib().mtb_tune_reset()
+
+
+def mtb_test_fail_launch(after: int) -> None:
+    """Make this thread's launch after `after` successful ones fail, once (tests only)."""
+    _check("mtb_test_fail_launch", lib().mtb_test_fail_launch(int(after)))
 
 
 def mtb_apply_shifts(images, shifts: torch.Tensor, fill: int = MTB_FILL_ZERO, out=None,

@@ -112,6 +112,9 @@ int current_device_cus()
 
 mtb_status device_status(hipError_t e) { return e == hipSuccess ? MTB_OK : MTB_ERR_DEVICE; }
 
+// Launches of this thread still to succeed before an injected failure; -1: none.
+thread_local int t_fail_after = -1;
+
 // Alignment (16, 4 or 1 bytes) that every row start of an image has.
 int row_alignment(const uint8_t *p, int64_t stride)
 {
@@ -342,6 +345,16 @@ void quadrant_items(const uint8_t *ref, const uint8_t *mov, int32_t W, int32_t H
 }
 
 }  // namespace
+
+bool injected_launch_failure()
+{
+    if (t_fail_after < 0)
+        return false;
+    if (t_fail_after-- == 0)
+        return true;  // t_fail_after is now -1: one failure only
+    return false;
+}
+
 }  // namespace mtb
 
 using namespace mtb;
@@ -755,6 +768,12 @@ mtb_status mtb_tuned_shape(int32_t n, int32_t width, int32_t height, int64_t row
     if (!h_out || !tune_lookup(tune_key(n, width, height, levels, row_stride), &t))
         return MTB_ERR_INVALID_ARG;
     to_shape(t, h_out);
+    return MTB_OK;
+}
+
+mtb_status mtb_test_fail_launch(int32_t after)
+{
+    t_fail_after = after < 0 ? -1 : after;
     return MTB_OK;
 }
 

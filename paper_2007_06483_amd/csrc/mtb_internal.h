@@ -166,9 +166,15 @@ ProfEvents prof_take(const char *name);
 void prof_commit(const char *name, const ProfEvents &ev, hipError_t launched);
 
 // Launches k<<<grid, block, 0, s>>>(a), timed when profiling is on.
+// Failure injection for tests (mtb_test_fail_launch): true when this launch
+// is to fail without being issued.
+bool injected_launch_failure();
+
 template <typename A>
 hipError_t launch_kernel(const char *name, void (*k)(A), dim3 grid, dim3 block, hipStream_t s, A a)
 {
+    if (injected_launch_failure())
+        return hipErrorLaunchFailure;
     const ProfEvents ev = prof_take(name);
     void *args[] = {&a};
     const hipError_t e = hipExtLaunchKernel((const void *)k, grid, block, args, 0, s, ev.start, ev.stop, 0);
