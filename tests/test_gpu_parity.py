@@ -176,6 +176,16 @@ def test_align_pair_level_counts(mtb, L):
     _check_pair(mtb, ref, mov, L)
 
 
+def test_align_pair_most_levels(mtb):
+    # As many levels as the size allows: the coarsest level is 1 x 1, the
+    # three coarsest are searched exhaustively and nine more are fine.
+    w, h = 1100, 1030
+    L = mtb.mtb_max_levels(w, h)
+    assert L == 11
+    ref, mov, _ = synth.make_rect_pair(w, h, 80, 333, 200)
+    _check_pair(mtb, ref, mov, L)
+
+
 def test_align_pair_degenerate(mtb):
     flat = np.full((96, 128, 3), 77, np.uint8)
     want = _check_pair(mtb, flat, flat, 4)
