@@ -520,7 +520,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the alignment path has no multi-GPU mode "
-              "(stacks are independent; see DESIGN.md for how it would shard).", file=sys.stderr)
+              "(stacks are independent, so it would shard by stack: each GPU aligns whole stacks, "
+              "with no exchange between GPUs).", file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0 or args.event_every < 1:
         ap.error("--steps and --event-every must be >= 1 and --warmup >= 0")
