@@ -10,9 +10,17 @@ Workload (default): seven 6000x4000 RGB exposures 2^-3..2^3, 7 levels (+-127 px)
 synthetic blob scene with 5% pooled saturation, moving images translated by
 seeded shifts in [-100, 100].  Megapixels count every input image.
 
+Other workloads (--workload): the same stack chained (each image against its
+neighbour towards the reference) or through 255/0 byte maps; single pairs
+4096x3072 and 512x384; 64 pairs of uneven sizes through mtb_align_batch (with
+its HIP-graph replay and the plain per-pair sequence); served Poisson arrivals
+of exposure stacks (device- and host-staged, with saturation sweeps);
+translating the stack by its shifts; the quadrant rotation check of the
+stack's six pairs.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--workload NAME] [--tune]
 """
 
 import argparse
