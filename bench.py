@@ -418,7 +418,6 @@ def run_served(args, mtb, synth, torch, np, dev):
     base = synth.make_serve_base(BW, BH, 5)
     base_dev = [torch.from_numpy(b).to(dev) for b in base]
     base_host = [torch.from_numpy(b).pin_memory() for b in base] if args.serve_host_seconds > 0 else None
-    del base
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     def requests(seed, rate, seconds, host):
@@ -438,13 +437,18 @@ def run_served(args, mtb, synth, torch, np, dev):
     pool = torch.empty(pool_bytes, dtype=torch.uint8, device=dev)
     execute, poll = gpu_executor(pool, slots)
 
-    def serve(rate, seconds, seed, host=False):
+    kept = {}
+
+    def serve(rate, seconds, seed, host=False, keep=False):
         reqs = requests(seed, rate, seconds, host)
         srv = Server(pool_bytes, slots, execute, poll)
         t_run = time.perf_counter()
         res = srv.run(reqs)
         torch.cuda.synchronize()
         t_run = time.perf_counter() - t_run
+        if keep:
+            kept["specs"] = synth.serve_requests(seed, rate, seconds, BW, BH)
+            kept["results"] = {r.rid: (r.shifts.cpu().numpy(), r.errs.cpu().numpy()) for r in res}
         lat = [r.latency * 1e3 for r in res]
         span = max(r.completed for r in res) - min(r.arrival for r in res)
         mp = sum(q.megapixels for q in reqs)
@@ -459,8 +463,35 @@ def run_served(args, mtb, synth, torch, np, dev):
 
     serve(200.0, 0.5, 99)  # warm-up
     log(f"serving Poisson(200/s) for {args.serve_seconds:.0f} s ...")
-    main_run = serve(200.0, args.serve_seconds, 5)
+    main_run = serve(200.0, args.serve_seconds, 5, keep=True)
     log(json.dumps(main_run))
+    cpu = None
+    if not args.no_cpu_baseline:
+        # A seeded sample of the served requests (the first 64) checked against
+        # the CPU oracle and timed on the host cores.
+        import oracle
+
+        log("checking and timing the CPU oracle on a sample of the served requests ...")
+        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        same, mp_cpu, done, t_cpu, most = True, 0.0, 0, 0.0, 1
+        for r in kept["specs"][:64]:
+            most = max(most, min(threads, r["n"]))  # threads a stack can keep busy
+            host = [np.ascontiguousarray(synth.serve_crop(base, r, i)) for i in range(r["n"])]
+            t = time.perf_counter()
+            want = oracle.align_stack(host, r["levels"], ref_index=r["n"] // 2, threads=threads)
+            t_cpu += time.perf_counter() - t
+            got_s, got_e = kept["results"][r["rid"]]
+            same = same and bool(np.array_equal(got_s, want["shifts"]) and
+                                 np.array_equal(got_e.astype(np.int64), want["errs"]))
+            mp_cpu += r["n"] * r["width"] * r["height"] / 1e6
+            done += 1
+            if t_cpu >= args.cpu_seconds and done >= 8:
+                break
+        cpu = {"value": round(mp_cpu / t_cpu, 3), "unit": "MP/s", "cores": most, "kind": "oracle",
+               "sample": f"the first {done} requests of the served run ({mp_cpu:.0f} MP) in {t_cpu:.2f} s, "
+                         f"each stack's images, then pairs, over up to {most} threads",
+               "parity_vs_gpu": same}
+        log(json.dumps(cpu))
     sweep = []
     for rate in (800.0, 1600.0, 3200.0, 6400.0, 12800.0):
         sweep.append(serve(rate, 3.0, 50 + int(rate)))
@@ -496,6 +527,9 @@ def run_served(args, mtb, synth, torch, np, dev):
         "host_staged": {"staging": "host (pinned base, mtb_stage_rgb per image inside each request)",
                         "served": host_run, "saturation_sweep": host_sweep},
     }
+    if cpu is not None:
+        result["cpu_baseline"] = {k: v for k, v in cpu.items() if k != "parity_vs_gpu"}
+        result["parity_vs_oracle"] = cpu["parity_vs_gpu"]
     print(json.dumps(result), flush=True)
 
 
