@@ -277,6 +277,29 @@ def run_batch(args, mtb, synth, torch, np, dev):
         "plain_per_pair": {"ms_per_step": round(ms_plain, 4), "MPps": round(mp_total / (ms_plain / 1e3), 1),
                            "same_results": same},
     }
+    if not args.no_cpu_baseline:
+        # The whole batch on the CPU oracle: pairs spread over the host cores.
+        import concurrent.futures
+
+        import oracle
+
+        log("timing the CPU oracle on the whole batch ...")
+        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        t = time.perf_counter()
+        def one(it):
+            w = oracle.align_pair(it[0], it[1], it[3])
+            return {"shift": w["shift"], "err": w["err"]}  # drop the pyramids at once
+
+        with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+            want = list(ex.map(one, batch))
+        dt = time.perf_counter() - t
+        got_s, got_e = shifts.cpu().numpy(), errs.cpu().numpy().astype(np.int64)
+        result["cpu_baseline"] = {"value": round(mp_total / dt, 3), "unit": "MP/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"the whole batch ({n} pairs, {mp_total:.0f} MP) once in {dt:.2f} s, "
+                                            f"pairs spread over {threads} threads"}
+        result["parity_vs_oracle"] = bool(
+            all(tuple(got_s[k]) == w["shift"] and got_e[k] == w["err"] for k, w in enumerate(want)))
     print(json.dumps(result), flush=True)
 
 
