@@ -13,13 +13,18 @@
  * Conventions for every call:
  *   - Memory.  Every pointer named d_* is device memory owned by the caller;
  *     the library allocates no device memory and keeps no state between
- *     calls.  Host arrays are named h_*.
+ *     calls apart from the launch-shape table that mtb_tune_stack and
+ *     mtb_set_shape fill (it changes speed, never results).  Host arrays are
+ *     named h_*.
  *   - Streams.  `stream` is a hipStream_t passed as void* (NULL is the null
  *     stream).  All device work is enqueued on it and runs asynchronously;
  *     results are valid once the stream has reached the call's work.
- *   - Errors.  Arguments are validated before anything is enqueued; on any
- *     error status nothing has been enqueued.  A failed kernel launch
- *     returns MTB_ERR_DEVICE.  No call aborts or throws.
+ *   - Errors.  Arguments are validated before anything is enqueued; on a
+ *     validation error (MTB_ERR_INVALID_ARG, MTB_ERR_WORKSPACE,
+ *     MTB_ERR_UNSUPPORTED) nothing has been enqueued.  A failed kernel launch
+ *     returns MTB_ERR_DEVICE: kernels enqueued before it still run and the
+ *     call's outputs are undefined, and the next call on the same buffers
+ *     starts afresh.  No call aborts or throws.
  *   - Images.  An RGB image is `height` rows of `width` interleaved R,G,B
  *     bytes; row y starts at byte y * row_stride (row_stride >= 3 * width).
  *     width * height must be below 2^31.
@@ -29,8 +34,9 @@
  *     +-(2^levels - 1) pixels per axis.
  *   - Shifts.  A shift (dx, dy) is what to apply to the moving image to align
  *     it with the reference: aligned[y][x] = moving[y - dy][x - dx].
- *   - Thread safety.  Calls are reentrant; calls on one stream that share an
- *     output buffer are ordered by the stream.
+ *   - Thread safety.  Calls are reentrant and may come from several host
+ *     threads at once (the shared caches and the shape table are guarded);
+ *     calls on one stream that share a buffer are ordered by the stream.
  */
 #ifndef MTB_H
 #define MTB_H
@@ -222,7 +228,8 @@ mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int
  * round of the workgroups the device holds at once, and the rows each row
  * stream of k_search_fine covers at every level (0: the built-in rule, the
  * fewest rows that keep one level's grid within one resident round).
- * Shapes are kept per (n, width, height, levels, row_stride mod 16 class) in
+ * Shapes are kept per (n, width, height, levels, whether row_stride is a
+ * multiple of 16, else of 4, else neither) in
  * a process-wide table guarded by a mutex; mtb_align_stack and
  * mtb_align_stack_chained use the table's shape for their key, the built-in
  * shape otherwise.
