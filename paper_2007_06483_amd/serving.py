@@ -215,13 +215,16 @@ def widen_for_dma(im):
     multiple of 4.  Returns (im, 0) when the frame does not allow it.
     """
     h, w = int(im.shape[0]), int(im.shape[1])
-    rs = int(im.stride(0))
+    rs = int(im.stride(0))                 # the frame's row length in bytes
     off = int(im.storage_offset())
     frame_w = rs // 3
-    x_byte = off % rs
-    if rs % 12 != 0 or x_byte % 3 != 0 or im.data_ptr() % 4 != (3 * (x_byte // 3)) % 4:
+    x_byte = off % rs                      # where the crop starts within its row
+    if rs % 12 != 0 or x_byte % 3 != 0:    # rows of whole 4-pixel groups, crop on a pixel
         return im, 0
     x = x_byte // 3
+    row_start = im.data_ptr() - 3 * x      # address of the frame row's first byte
+    if row_start % 4 != 0:
+        return im, 0
     xa = x - x % 4
     xe = -(-(x + w) // 4) * 4
     if xe > frame_w:
