@@ -567,7 +567,7 @@ def main():
                              "batch64_uneven",
                              "served_poisson200", "apply7_6000x4000", "quadrants7_6000x4000"])
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
-    ap.add_argument("--serve-slots", type=int, default=4, help="served mode: stacks in flight at most")
+    ap.add_argument("--serve-slots", type=int, default=8, help="served mode: stacks in flight at most")
     ap.add_argument("--serve-host-seconds", type=float, default=20.0,
                     help="served mode: length of the host-staged run (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
