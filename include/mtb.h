@@ -67,7 +67,9 @@ typedef enum mtb_status {
  *   gray level l: level_height[l] rows of gray_pitch[l] bytes at gray_offset[l];
  *     byte x of row y is the gray value of pixel (x, y) for x < level_width[l]
  *     (the bytes past level_width[l] are padding with no defined value);
- *   histogram: uint32 hist[levels][256] at hist_offset (Section III-B).
+ *   histogram: uint32 hist[levels][256] at hist_offset (Section III-B);
+ *   the bytes from the end of the histogram to pyramid_bytes are scratch the
+ *   build uses while merging histograms, with no defined value afterwards.
  * Bitmaps buffer (written by mtb_bitmaps):
  *   the first 256 bytes are a guard with no defined value;
  *   level l threshold bitmap T and exclusion bitmap E: each level_height[l]

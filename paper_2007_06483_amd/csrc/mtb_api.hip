@@ -45,6 +45,8 @@ bool make_geometry(int32_t W, int32_t H, int32_t L, Geometry *g)
     }
     g->hist_off = off;
     off = align_up(off + (int64_t)L * 256 * 4, kAlign);
+    g->hmerge_off = off;
+    off = align_up(off + 4 * kHMergeWords, kAlign);
     g->pyramid_bytes = off;
     // The search reads up to two words either side of a bitmap row (and masks
     // them out): a leading guard keeps those reads inside the buffer before
@@ -164,7 +166,7 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
 
     for (int i = 0; i < n; ++i) {
         zero.ptr[zero.count] = (uint32_t *)(pyr0 + i * g.pyramid_bytes + g.hist_off);
-        zero.words[zero.count++] = (int64_t)g.L * 256;
+        zero.words[zero.count++] = (g.pyramid_bytes - g.hist_off) / 4;  // histograms and merge scratch
     }
     zero.ptr[zero.count] = state;
     zero.words[zero.count++] = sstride * npairs + kTicketWords;  // every pair's search state, then the tickets
@@ -457,7 +459,7 @@ mtb_status mtb_build_pyramid(const uint8_t *d_rgb, int32_t width, int32_t height
     ZeroArgs z;
     memset(&z, 0, sizeof(z));
     z.ptr[0] = (uint32_t *)(pyr + g.hist_off);
-    z.words[0] = (int64_t)levels * 256;
+    z.words[0] = (g.pyramid_bytes - g.hist_off) / 4;  // histograms and merge scratch
     z.count = 1;
     hipError_t e = launch_zero(z, s);
     if (e != hipSuccess)

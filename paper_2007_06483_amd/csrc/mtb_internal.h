@@ -17,6 +17,16 @@ constexpr int kAlign = 256;
 // Pass 1 fuses this many pyramid levels per workgroup tile; the tile is
 // kTileH = 2^(kFused-1) rows by kTileW columns of level 0.
 constexpr int kFused = 7;
+// Accelerator complex dies (XCDs) of the device, each with its own L2.
+constexpr int kXcds = 8;
+// k_pyramid's histogram merge scratch per image: one uint32[kFused][256] copy
+// per XCD, then kXcds tile tickets and one XCD ticket.  It follows the
+// histograms, so that one range from hist_off to the end of the pyramid
+// buffer clears both.
+constexpr int64_t kHMergeWords = (int64_t)kXcds * kFused * 256 + 64;
+// Launches with at least this many workgroups per image merge histograms
+// through the per-XCD copies.
+constexpr int kMergeMinWgsPerImage = 192;
 constexpr int kTileH = 64;
 constexpr int kTileW = 256;
 
@@ -45,6 +55,7 @@ struct Geometry {
     int32_t W, H, L, pad_;
     LevelGeom lv[kMaxLevels];
     int64_t hist_off;       // uint32[L][256] in the pyramid buffer
+    int64_t hmerge_off;     // pyramid buffer: k_pyramid's histogram merge scratch (kHMergeWords)
     int64_t pyramid_bytes;
     int64_t med_off;        // int32[L] in the bitmaps buffer
     int64_t bitmaps_bytes;
@@ -66,7 +77,7 @@ struct PyramidArgs {
     int32_t tiles_x, tiles_y;
     int32_t xcd_tiles;       // tiles of each XCD's contiguous share of the work
     int32_t align;           // 16, 4 or 1: alignment every RGB row start is known to have
-    int32_t pad_;
+    int32_t merge;           // 1: histograms merged through per-XCD copies (see k_pyramid)
     Geometry g;
 };
 

@@ -19,8 +19,6 @@ namespace mtb {
 namespace {
 
 constexpr int kWave = 64;
-// Accelerator complex dies (XCDs) of the device, each with its own L2.
-constexpr int kXcds = 8;
 // Fine search: rows per batch and batches in flight per stream (rows per
 // stream is a multiple of their product).
 constexpr int kSearchBatch = 1;
@@ -65,6 +63,18 @@ __device__ __forceinline__ void gray4(uint32_t a, uint32_t b, uint32_t c, uint32
 __device__ __forceinline__ uint32_t pack4(const uint32_t *v)
 {
     return v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+}
+
+// Loads and stores of words that several workgroups (on different XCDs) exchange
+// within one launch: agent-scope atomics, performed at the coherence point.
+__device__ __forceinline__ uint32_t load_shared(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_shared(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Level-0 histogram privatisation: kH0Copies copies per wave; copies kHStride
@@ -118,6 +128,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     __shared__ uint32_t histc[kFused - 2][256];           // levels 2 .. 6, whole workgroup
     __shared__ uint32_t lvl4[2][kDefer][4][16];           // level-4 pixels of deferred tiles, two rings
     __shared__ int2 ring_pos[2][kDefer];                  // level-0 origin of each deferred tile
+    __shared__ int s_merge;                               // this workgroup merges the image's copies
 
     const int tid = threadIdx.x;
     const int wave = wave_id();
@@ -189,14 +200,37 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     };
     int bank = 0, parked = 0;
 
-    auto flush = [&](int img) {
+    // Tiles of image img in XCD x's share of the tiles.
+    auto xcd_tiles_of = [&](int x, int img) -> int64_t {
+        const int64_t ib = (int64_t)img * per_image, ie = ib + per_image;
+        int64_t b = (int64_t)x * a.xcd_tiles, e = b + a.xcd_tiles < total ? b + a.xcd_tiles : total;
+        b = b > ib ? b : ib;
+        e = e < ie ? e : ie;
+        return e > b ? e - b : 0;
+    };
+
+    // Adds the workgroup's histograms of image img (from `tiles` of its tiles)
+    // into the image's histogram, or with a.merge into its XCD's copy in the
+    // merge scratch, summed into the histogram by the workgroup that adds the
+    // image's last tiles.  When hundreds of workgroups of an image flush at
+    // the same moment (a few tiles each), their atomics on the histogram's
+    // few cache lines queue behind each other; the copies divide that queue
+    // by the XCD count, at the price of a ticket round trip per flush.  The
+    // tickets follow the ordering of last_workgroup: agent-scope atomics
+    // only, each thread's own operations acknowledged before the workgroup
+    // takes its ticket.  The tile ticket of each XCD counts tiles; the
+    // workgroup that completes its XCD's tiles of the image takes a ticket
+    // among the XCDs holding tiles of the image, and the last of those merges.
+    auto flush = [&](int img, int tiles) {
         __syncthreads();
         if (parked > 0) {
             drain(img, bank, parked);
             parked = 0;
             __syncthreads();
         }
-        uint32_t *gh = (uint32_t *)(a.pyr[img] + g.hist_off);
+        const int xcd = blockIdx.x % kXcds;
+        uint32_t *merge = (uint32_t *)(a.pyr[img] + g.hmerge_off);
+        uint32_t *gh = a.merge ? merge + xcd * kFused * 256 : (uint32_t *)(a.pyr[img] + g.hist_off);
         for (int l = 0; l < fused; ++l) {
             uint32_t s = 0;
             if (l == 0) {
@@ -213,6 +247,32 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
             }
             if (s)
                 atomicAdd(gh + l * 256 + tid, s);
+        }
+        if (!a.merge) {
+            __syncthreads();
+            return;
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t *tickets = merge + kXcds * kFused * 256;
+            s_merge = 0;
+            if ((int64_t)atomicAdd(tickets + xcd, (uint32_t)tiles) + tiles == xcd_tiles_of(xcd, img)) {
+                uint32_t holders = 0;
+                for (int x = 0; x < kXcds; ++x)
+                    holders += xcd_tiles_of(x, img) > 0;
+                s_merge = atomicAdd(tickets + kXcds, 1u) + 1 == holders;
+            }
+        }
+        __syncthreads();
+        if (s_merge) {
+            uint32_t *hist = (uint32_t *)(a.pyr[img] + g.hist_off);
+            for (int l = 0; l < fused; ++l) {
+                uint32_t v = 0;
+                for (int x = 0; x < kXcds; ++x)
+                    v += load_shared(merge + (x * kFused + l) * 256 + tid);
+                hist[l * 256 + tid] = v;
+            }
         }
         __syncthreads();
     };
@@ -235,15 +295,17 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
             load_rgb16(a.rgb[img], a.stride, x0, Y0 + 16 * wave + 4 * by, g.H, q);
     }
 
-    int cur = -1;
+    int cur = -1, cur_tiles = 0;
     for (int64_t t = t0; t < t1; t += slots) {
         int img, X0, Y0;
         locate(t, img, X0, Y0);
         if (img != cur) {
             if (cur >= 0)
-                flush(cur);
+                flush(cur, cur_tiles);
             cur = img;
+            cur_tiles = 0;
         }
+        ++cur_tiles;
         const int x0 = X0 + 16 * bx, y0 = Y0 + 16 * wave + 4 * by;
         const uint8_t *rgb = a.rgb[img];
         uint8_t *pyr = a.pyr[img];
@@ -434,7 +496,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
         }
     }
     if (cur >= 0)
-        flush(cur);
+        flush(cur, cur_tiles);
 }
 
 // Levels kFused .. L-1, each the floor 2x2 mean of the level below; one
@@ -1038,18 +1100,6 @@ __device__ __forceinline__ int argmin9(const uint32_t *c)
         if (c[i] < c[best])
             best = i;
     return best;
-}
-
-// Loads and stores of words that several workgroups (on different XCDs) exchange
-// within one launch: agent-scope atomics, performed at the coherence point.
-__device__ __forceinline__ uint32_t load_shared(const uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void store_shared(uint32_t *p, uint32_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint32_t *pair_state(const SearchArgs &a, int p)
@@ -1707,6 +1757,7 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s, int slo
     slots = slots > share ? share : (slots < 1 ? 1 : slots);
     a.xcd_tiles = (int32_t)share;
     const int blocks = (int)(slots * kXcds);
+    a.merge = blocks >= kMergeMinWgsPerImage * a.n;
     hipError_t e = launch_kernel("k_pyramid", k_pyramid, dim3(blocks), dim3(256), s, a);
     if (e != hipSuccess || a.g.L <= kFused)
         return e;

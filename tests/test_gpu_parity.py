@@ -250,6 +250,22 @@ def test_stack_intermediates_match_oracle(mtb):
             assert not tp.any() and not ep.any()
 
 
+@pytest.mark.parametrize("w,h,n", [(2048, 1536, 2), (2100, 1700, 1), (1300, 1100, 2)])
+def test_stack_histograms_many_workgroups_per_image(mtb, w, h, n):
+    # Launches with a few hundred pyramid workgroups per image (the first two
+    # cases) merge the histograms through per-XCD copies and tile tickets;
+    # the third stays below that and adds into the histograms directly.
+    # Both must give the oracle's histograms, medians and shifts.
+    imgs, _, _ = synth.make_stack(w, h, n, 40, 700 + w + n, 20, sat_frac=0.05)
+    L = 6
+    got, want = _check_stack(mtb, imgs, L)
+    lay = mtb.mtb_get_layout(w, h, L)
+    pyrs, bms = stack_workspace(got["workspace"].cpu().numpy(), got["workspace"].data_ptr(), n, lay)
+    for i, p in enumerate(want["pyramids"]):
+        assert np.array_equal(histograms(pyrs[i], lay), p.hist), f"histograms of image {i}"
+        assert np.array_equal(medians(bms[i], lay), p.median), f"medians of image {i}"
+
+
 def test_repeated_runs_are_bit_identical(mtb):
     imgs, _, _ = synth.make_stack(800, 600, 5, 60, 91, 40, sat_frac=0.05)
     d = [_to_dev(im) for im in imgs]
