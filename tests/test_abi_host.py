@@ -78,6 +78,10 @@ def test_layout_is_consistent(mtb, w, h, L):
         end = lay.gray_offset[l] + lay.gray_pitch[l] * lay.level_height[l]
     assert lay.hist_offset >= end and lay.hist_offset % 256 == 0
     assert lay.pyramid_bytes >= lay.hist_offset + 1024 * L
+    # After the histograms: the pyramid pass's merge scratch, one uint32[7][256]
+    # copy per XCD (8) and the tickets; the buffer ends on a 256-byte boundary.
+    assert lay.pyramid_bytes >= lay.hist_offset + 1024 * L + 8 * 7 * 1024
+    assert lay.pyramid_bytes % 256 == 0
     assert lay.pyramid_bytes == mtb.mtb_pyramid_bytes(w, h, L)
     end = 0
     for l in range(L):
