@@ -81,23 +81,19 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def load_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
-    taken on this kernel's launch in this workload and the kernel sources are unchanged.
-    (The chained and byte-map variants of a stack launch the same k_pyramid.)"""
+def load_traffic(workload):
+    """HBM bytes per launch of every kernel of one step, from the committed
+    rocprofv3 counter runs, if they were taken on this workload and the kernel
+    sources are unchanged since; {} otherwise.  Keys are kernel names (search
+    launches carry their level: "k_search_fine@l0", ...)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
-    base = workload
-    for suffix in ("_chained", "_bytemaps"):
-        if kernel == "k_pyramid" and base.endswith(suffix):
-            base = base[: -len(suffix)]
-    if (t.get("kernel") != kernel or t.get("workload") != base
-            or t.get("kernel_source_sha256") != kernel_source_sha256()):
-        return None
-    return t.get("traffic_bytes_per_launch")
+        return {}
+    if t.get("workload") != workload or t.get("kernel_source_sha256") != kernel_source_sha256():
+        return {}
+    return {k: v["traffic_bytes_per_launch"] for k, v in t.get("kernels", {}).items()}
 
 
 def cpu_baseline(imgs, levels, ref, mp_total, max_threads, min_seconds, chained=False):
@@ -573,6 +569,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="let mtb_tune_stack pick the launch shape before timing (default: built-in shape)")
+    ap.add_argument("--shape", default=None,
+                    help="stack workloads: a launch shape (JSON object of mtb_launch_shape fields) "
+                         "stored with mtb_set_shape before timing")
     ap.add_argument("--event-every", type=int, default=4,
                     help="time the dominant kernel with HIP events in every N-th timed step")
     ap.add_argument("--cpu-threads", type=int, default=16)
@@ -643,6 +642,13 @@ def main():
     # same results.  Without it the built-in shape runs, as in the committed
     # rocprofv3 summaries (the tuner's trial launches would mix into them).
     shape = None
+    if args.shape and not bytemaps:
+        full = {"pyramid_slots_pct": 100, "bitmaps_blocks_pct": 100, "search_rows": [], "overlap": 1,
+                "bitmaps0_blocks_pct": 67}
+        full.update(json.loads(args.shape))
+        mtb.mtb_set_shape(n, W, H, int(d_imgs[0].stride(0)), L, full)
+        shape = dict(mtb.mtb_tuned_shape(n, W, H, int(d_imgs[0].stride(0)), L), step_ms=0.0, default_ms=0.0)
+        log(f"launch shape: {json.dumps(shape)}")
     if not bytemaps and args.tune:
         shape = mtb.mtb_tune_stack(d_imgs, L, ref_index=ref, workspace=ws, shifts=shifts, errs=errs)
         log(f"launch shape: {json.dumps(shape)}")
@@ -692,6 +698,8 @@ def main():
     avg_s = total_ms / launches / 1e3
     achieved = algo[dominant] / avg_s / 1e9
     copy_gbps = measured_copy_GBps(torch, dev)
+    traffic = load_traffic(args.workload)
+    step_gbps = algo["step"] / (ms_per_step / 1e3) / 1e9
     roofline = {
         "bound": "hbm",
         "kernel": dominant,
@@ -699,12 +707,18 @@ def main():
         "peak": PEAK_HBM_GBPS,
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBPS, 4),
-        "traffic": load_traffic(dominant, args.workload),
+        "traffic": traffic.get(dominant),
         "avg_launch_us": round(avg_s * 1e6, 2),
         "evented_launches": launches,
         "algorithmic_bytes_per_launch": algo[dominant],
         "copy_measured": round(copy_gbps, 1),
         "frac_of_copy": round(achieved / copy_gbps, 4),
+        # The whole step against the same peak: model bytes of every kernel of
+        # the step over the timed step time.
+        "step_achieved": round(step_gbps, 1),
+        "step_frac": round(step_gbps / PEAK_HBM_GBPS, 4),
+        "step_model_bytes": algo["step"],
+        "traffic_by_kernel": traffic or None,
     }
 
     # Paper-comparable end-to-end time: host (pinned) -> device copies included.
@@ -760,9 +774,11 @@ def main():
                     "max": round(step_us[-1], 1), "steps": len(step_us)},
         "e2e_incl_h2d": {"ms_per_step": round(e2e_ms, 3), "MPps": round(mp_total / (e2e_ms / 1e3), 1)},
         "launch_shape": {"tuned": False, "pyramid_slots_pct": 100, "bitmaps_blocks_pct": 100,
-                         "search_rows": "built-in rule"} if shape is None else {
-            "tuned": True, "pyramid_slots_pct": shape["pyramid_slots_pct"],
+                         "search_rows": "built-in rule", "overlap": 1, "bitmaps0_blocks_pct": 67}
+        if shape is None else {
+            "tuned": bool(args.tune), "pyramid_slots_pct": shape["pyramid_slots_pct"],
             "bitmaps_blocks_pct": shape["bitmaps_blocks_pct"], "search_rows": shape["search_rows"][:L],
+            "overlap": shape["overlap"], "bitmaps0_blocks_pct": shape["bitmaps0_blocks_pct"],
             "tuner_step_ms": round(shape["step_ms"], 4), "tuner_default_ms": round(shape["default_ms"], 4)},
     }
 

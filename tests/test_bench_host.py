@@ -1,5 +1,6 @@
 """Host logic of bench.py: the one-GPU guard, the algorithmic byte model and the
-rule that stored counter figures apply only to the launch they were taken on."""
+rule that stored counter figures apply only to the workload and kernel sources
+they were taken on."""
 
 import json
 import os
@@ -37,20 +38,17 @@ def test_algorithmic_bytes_of_the_stack_workload():
     assert bench.pyramid_bytes(W, H, L) * n == per["k_pyramid"]
 
 
-def test_stored_traffic_applies_only_to_its_own_launch(tmp_path, monkeypatch):
+def test_stored_traffic_applies_only_to_its_own_workload(tmp_path, monkeypatch):
     f = tmp_path / "traffic.json"
-    f.write_text(json.dumps({"kernel": "k_pyramid", "workload": "stack7_6000x4000",
-                             "kernel_source_sha256": bench.kernel_source_sha256(),
-                             "traffic_bytes_per_launch": 123}))
+    kernels = {"k_pyramid": {"traffic_bytes_per_launch": 123}, "k_bitmaps": {"traffic_bytes_per_launch": 45}}
+    f.write_text(json.dumps({"workload": "stack7_6000x4000", "kernel_source_sha256": bench.kernel_source_sha256(),
+                             "kernels": kernels}))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.load_traffic("k_pyramid", "stack7_6000x4000") == 123
-    assert bench.load_traffic("k_pyramid", "stack7_6000x4000_chained") == 123   # same k_pyramid launch
-    assert bench.load_traffic("k_pyramid", "stack7_6000x4000_bytemaps") == 123
-    assert bench.load_traffic("k_pyramid", "pair_4096x3072") is None
-    assert bench.load_traffic("k_pyramid", "quadrants7_6000x4000") is None
-    assert bench.load_traffic("k_bitmaps", "stack7_6000x4000") is None
-    f.write_text(json.dumps({"kernel": "k_pyramid", "workload": "stack7_6000x4000",
-                             "kernel_source_sha256": "0" * 64, "traffic_bytes_per_launch": 123}))
-    assert bench.load_traffic("k_pyramid", "stack7_6000x4000") is None       # kernels changed since
+    assert bench.load_traffic("stack7_6000x4000") == {"k_pyramid": 123, "k_bitmaps": 45}
+    assert bench.load_traffic("stack7_6000x4000_chained") == {}    # another launch sequence
+    assert bench.load_traffic("pair_4096x3072") == {}
+    f.write_text(json.dumps({"workload": "stack7_6000x4000", "kernel_source_sha256": "0" * 64,
+                             "kernels": kernels}))
+    assert bench.load_traffic("stack7_6000x4000") == {}            # kernels changed since
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
-    assert bench.load_traffic("k_pyramid", "stack7_6000x4000") is None
+    assert bench.load_traffic("stack7_6000x4000") == {}

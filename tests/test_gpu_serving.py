@@ -69,6 +69,65 @@ def test_served_results_equal_results_alone(mtb):
         assert np.array_equal(got.errs.cpu().numpy().astype(np.int64), want["errs"]), r["rid"]
 
 
+@pytest.mark.timeout(900)
+def test_served_full_size_requests(mtb):
+    """Requests at the served workload's own ranges: 3-9 exposures of 1-48 MP
+    (log-uniform, 3:2), up to 7 levels, cut from the 8704x5888 nine-exposure base
+    scene.  The first eight arrive together, five of them 8 MP or more, so several
+    large stacks are in flight at once.  Every result must equal that stack
+    aligned alone, and a seeded sample of eight (the four largest and four drawn
+    from the rest) must equal the oracle's."""
+    import concurrent.futures
+
+    from paper_2007_06483_amd.serving import Request, Server, gpu_executor
+
+    BW, BH = 8704, 5888
+    base = synth.make_serve_base(BW, BH, 5)
+    base_dev = [torch.from_numpy(b).to(DEV) for b in base]
+    specs = synth.serve_requests(26, 200.0, 0.15, BW, BH)
+    assert len(specs) >= 30
+    assert max(r["width"] * r["height"] for r in specs) > 40e6
+    reqs = []
+    for k, r in enumerate(specs):
+        imgs = [synth.serve_crop(base_dev, r, i) for i in range(r["n"])]
+        ws = mtb.mtb_stack_workspace_bytes(r["n"], r["width"], r["height"], r["levels"])
+        reqs.append(Request(rid=r["rid"], arrival=0.0 if k < 8 else r["arrival"], images=imgs,
+                            levels=r["levels"], workspace_bytes=ws))
+    slots = 8
+    pool_bytes = slots * max(q.workspace_bytes for q in reqs) + 4096
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device=DEV)
+    execute, poll = gpu_executor(pool, slots)
+    srv = Server(pool_bytes, slots, execute, poll)
+    results = srv.run(reqs)
+    torch.cuda.synchronize()
+    assert len(results) == len(reqs)
+    # At least three stacks of 8 MP or more overlapped in time.
+    big = [res for res, r in zip(results, specs) if r["width"] * r["height"] >= 8e6]
+    overlap = max(sum(1 for o in big if o.admitted <= b.admitted < o.completed) for b in big)
+    assert overlap >= 3, overlap
+    for q, res in zip(reqs, results):
+        alone = mtb.mtb_align_stack(q.images, q.levels)
+        torch.cuda.synchronize()
+        assert torch.equal(res.shifts, alone["shifts"]), q.rid
+        assert torch.equal(res.errs, alone["errs"]), q.rid
+    del pool, base_dev
+    order = sorted(range(len(specs)), key=lambda k: -specs[k]["width"] * specs[k]["height"] * specs[k]["n"])
+    rest = np.random.default_rng(26).choice(order[4:], 4, replace=False)
+    sample = order[:4] + sorted(int(k) for k in rest)
+
+    def one(k):
+        r = specs[k]
+        host = [np.ascontiguousarray(synth.serve_crop(base, r, i)) for i in range(r["n"])]
+        return oracle.align_stack(host, r["levels"], ref_index=r["n"] // 2, threads=2)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+        wants = list(ex.map(one, sample))
+    for k, want in zip(sample, wants):
+        got = results[specs[k]["rid"]]
+        assert np.array_equal(got.shifts.cpu().numpy(), want["shifts"]), k
+        assert np.array_equal(got.errs.cpu().numpy().astype(np.int64), want["errs"]), k
+
+
 def test_stage_rgb_copies_a_strided_host_view(mtb):
     base = torch.from_numpy(np.random.default_rng(11).integers(0, 256, (70, 150, 3), dtype=np.uint8)).pin_memory()
     view = base[5:65, 7:140]                       # rows 450 bytes apart, 133 pixels used

@@ -304,6 +304,35 @@ def test_search_reaches_exhaustive_minimum_on_tiny_planted_images():
     assert r["shift"] == winners[0] == (-tx, -ty)
 
 
+def test_cfg1_pair_brute_force_level0_surface():
+    """The 512x384 pair workload (40 blobs, 2^0 / 2^-2, 5 levels, shift range +-31):
+    its level-0 error over every shift in [-31, 31]^2, counted by padded slicing
+    (not the oracle's shift routine), has its minimum where the oracle's search
+    ends, and the oracle's level-0 error equals that minimum.
+
+    On this input the minimum (0) is reached by eight shifts, the planted answer
+    (-9, 4) among them: the threshold edges of the smooth blobs lie inside the
+    +-4 exclusion band, so no one-pixel move changes a counted pixel there, and
+    the tie-break picks the lowest (dy, dx) of the candidates the pyramid reaches.
+    """
+    w = synth.workload("pair_512x384")
+    (imgs, shifts, _), = w.stacks
+    r = oracle.align_pair(imgs[0], imgs[1], w.levels)
+    pr, pm = r["ref"], r["mov"]
+    R = 2 ** w.levels - 1
+    tr, er, tm, em = pr.tb(0), pr.eb(0), pm.tb(0), pm.eb(0)
+    surf = {(cx, cy): _brute_error(tr, er, tm, em, cx, cy)
+            for cy in range(-R, R + 1) for cx in range(-R, R + 1)}
+    best = min(surf.values())
+    assert r["err"] == best
+    assert surf[r["shift"]] == best
+    zero_set = sorted((c for c, v in surf.items() if v == best), key=lambda c: (c[1], c[0]))
+    planted = (-shifts[1][0], -shifts[1][1])
+    assert planted in zero_set
+    assert r["shift"] == zero_set[0] == (-10, 3)
+    assert len(zero_set) == 8
+
+
 # ---------------------------------------------------------------- stacks (Section III-B)
 
 def test_stack_is_independent_pairs_against_reference():
