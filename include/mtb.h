@@ -116,6 +116,17 @@ size_t mtb_pair_workspace_bytes(int32_t levels);
 size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32_t levels);
 
 /*
+ * Where mtb_align_stack (and the chained mode) leave each image's pyramid
+ * buffer and bitmaps buffer (layouts as described at mtb_layout) inside a
+ * workspace at d_workspace: h_pyramids[i] and h_bitmaps[i] receive device
+ * addresses inside that workspace, for i < n.  Nothing is read or written on
+ * the device.
+ * Errors: MTB_ERR_INVALID_ARG (null pointers, n, sizes or levels out of range).
+ */
+mtb_status mtb_stack_image_buffers(const void *d_workspace, int32_t n, int32_t width, int32_t height,
+                                   int32_t levels, void **h_pyramids, void **h_bitmaps);
+
+/*
  * Gray pyramid and per-level histograms of one RGB image (Section III-A:
  * gray conversion and the 2x pyramid; Section III-B: 256-bin histograms of
  * every level).  gray = (54 R + 183 G + 19 B) >> 8; each coarser level is the
@@ -282,6 +293,15 @@ void mtb_tune_reset(void);
  * faults on the device: the failing kernel is never launched.
  */
 mtb_status mtb_test_fail_launch(int32_t after);
+
+/*
+ * For tests of the pyramid's histogram merge: the workgroup count of the last
+ * k_pyramid launch made by the calling thread, and 1 if that launch merged
+ * histograms through per-XCD copies (launches with many workgroups per
+ * image), 0 if its workgroups added into the histograms directly.
+ * Errors: MTB_ERR_INVALID_ARG (a null pointer, or no launch yet on this thread).
+ */
+mtb_status mtb_test_last_pyramid(int32_t *h_blocks, int32_t *h_merged);
 
 /*
  * Translates every image of a stack by its shift (Section III-B: the shift

@@ -45,6 +45,8 @@ __all__ = [
     "mtb_tuned_shape",
     "mtb_tune_reset",
     "mtb_test_fail_launch",
+    "mtb_test_last_pyramid",
+    "mtb_stack_image_buffers",
     "mtb_quadrant_workspace_bytes",
     "mtb_align_quadrants",
     "MTB_FILL_ZERO",
@@ -202,6 +204,10 @@ def lib():
     L.mtb_tune_reset.restype = None
     L.mtb_test_fail_launch.argtypes = [i32]
     L.mtb_test_fail_launch.restype = ctypes.c_int
+    L.mtb_test_last_pyramid.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.mtb_test_last_pyramid.restype = ctypes.c_int
+    L.mtb_stack_image_buffers.argtypes = [P, i32, i32, i32, i32, ctypes.POINTER(P), ctypes.POINTER(P)]
+    L.mtb_stack_image_buffers.restype = ctypes.c_int
     L.mtb_stage_rgb.argtypes = [P, i64, i32, i32, P, i64, P]
     L.mtb_stage_rgb.restype = ctypes.c_int
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
@@ -438,6 +444,24 @@ def mtb_tune_reset() -> None:
 def mtb_test_fail_launch(after: int) -> None:
     """Make this thread's launch after `after` successful ones fail, once (tests only)."""
     _check("mtb_test_fail_launch", lib().mtb_test_fail_launch(int(after)))
+
+
+def mtb_test_last_pyramid() -> tuple:
+    """(workgroups, merged) of this thread's last k_pyramid launch (tests only)."""
+    blocks, merged = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check("mtb_test_last_pyramid", lib().mtb_test_last_pyramid(ctypes.byref(blocks), ctypes.byref(merged)))
+    return int(blocks.value), bool(merged.value)
+
+
+def mtb_stack_image_buffers(workspace: torch.Tensor, n: int, width: int, height: int, levels: int):
+    """Byte offsets into ``workspace`` of each image's (pyramid, bitmaps) buffer after mtb_align_stack."""
+    _device_u8(workspace, "workspace")
+    pyr = (ctypes.c_void_p * n)()
+    bms = (ctypes.c_void_p * n)()
+    _check("mtb_stack_image_buffers",
+           lib().mtb_stack_image_buffers(_ptr(workspace), n, width, height, levels, pyr, bms))
+    base = workspace.data_ptr()
+    return [(int(pyr[i]) - base, int(bms[i]) - base) for i in range(n)]
 
 
 def mtb_apply_shifts(images, shifts: torch.Tensor, fill: int = MTB_FILL_ZERO, out=None,

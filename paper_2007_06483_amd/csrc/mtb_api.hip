@@ -116,6 +116,8 @@ mtb_status device_status(hipError_t e) { return e == hipSuccess ? MTB_OK : MTB_E
 
 // Launches of this thread still to succeed before an injected failure; -1: none.
 thread_local int t_fail_after = -1;
+// Workgroups and merge mode of this thread's last k_pyramid launch; -1: none yet.
+thread_local int t_pyr_blocks = -1, t_pyr_merged = 0;
 
 // Alignment (16, 4 or 1 bytes) that every row start of an image has.
 int row_alignment(const uint8_t *p, int64_t stride)
@@ -348,6 +350,12 @@ void quadrant_items(const uint8_t *ref, const uint8_t *mov, int32_t W, int32_t H
 
 }  // namespace
 
+void note_pyramid_launch(int blocks, int merged)
+{
+    t_pyr_blocks = blocks;
+    t_pyr_merged = merged;
+}
+
 bool injected_launch_failure()
 {
     if (t_fail_after < 0)
@@ -437,6 +445,21 @@ size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32
         return 0;
     // pyramids, bitmaps, search state, ticket counters, plus slack to align the start
     return (size_t)(set_workspace_bytes(g, n, n - 1) + kAlign);
+}
+
+mtb_status mtb_stack_image_buffers(const void *d_workspace, int32_t n, int32_t width, int32_t height,
+                                   int32_t levels, void **h_pyramids, void **h_bitmaps)
+{
+    Geometry g;
+    if (!d_workspace || !h_pyramids || !h_bitmaps || n < 1 || n > kMaxStack ||
+        !make_geometry(width, height, levels, &g))
+        return MTB_ERR_INVALID_ARG;
+    uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
+    for (int i = 0; i < n; ++i) {
+        h_pyramids[i] = ws + i * g.pyramid_bytes;
+        h_bitmaps[i] = ws + n * g.pyramid_bytes + i * g.bitmaps_bytes;
+    }
+    return MTB_OK;
 }
 
 mtb_status mtb_build_pyramid(const uint8_t *d_rgb, int32_t width, int32_t height,
@@ -770,6 +793,15 @@ mtb_status mtb_tuned_shape(int32_t n, int32_t width, int32_t height, int64_t row
     if (!h_out || !tune_lookup(tune_key(n, width, height, levels, row_stride), &t))
         return MTB_ERR_INVALID_ARG;
     to_shape(t, h_out);
+    return MTB_OK;
+}
+
+mtb_status mtb_test_last_pyramid(int32_t *h_blocks, int32_t *h_merged)
+{
+    if (!h_blocks || !h_merged || t_pyr_blocks < 0)
+        return MTB_ERR_INVALID_ARG;
+    *h_blocks = t_pyr_blocks;
+    *h_merged = t_pyr_merged;
     return MTB_OK;
 }
 

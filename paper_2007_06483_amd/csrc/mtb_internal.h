@@ -180,6 +180,8 @@ void prof_commit(const char *name, const ProfEvents &ev, hipError_t launched);
 // Failure injection for tests (mtb_test_fail_launch): true when this launch
 // is to fail without being issued.
 bool injected_launch_failure();
+// Records the shape of the calling thread's last k_pyramid launch (tests).
+void note_pyramid_launch(int blocks, int merged);
 
 template <typename A>
 hipError_t launch_kernel(const char *name, void (*k)(A), dim3 grid, dim3 block, hipStream_t s, A a)

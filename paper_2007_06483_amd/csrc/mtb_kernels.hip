@@ -1715,16 +1715,18 @@ __global__ void k_quadrant_flag(QuadFlagArgs a)
 
 // ---------------------------------------------------------------- launchers
 
-// Workgroups of 256 threads of `kernel` that fit on one compute unit at once
-// (registers and LDS), from the runtime's occupancy calculator; cached.
-template <typename A>
-int resident_per_cu(void (*kernel)(A))
+// Workgroups of 256 threads of kernel K that fit on one compute unit at once
+// (registers and LDS), from the runtime's occupancy calculator; cached once
+// per kernel (each instantiation has its own cache, so kernels that share an
+// argument type do not share a value).
+template <auto K>
+int resident_per_cu()
 {
     static std::atomic<int> cached{0};
     int v = cached.load(std::memory_order_relaxed);
     if (v == 0) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, 256, 0) != hipSuccess || n < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, K, 256, 0) != hipSuccess || n < 1)
             n = 1;
         cached.store(n, std::memory_order_relaxed);
         v = n;
@@ -1753,11 +1755,12 @@ hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s, int slo
     // One round of resident workgroups (scaled by slots_pct); each XCD gets
     // the same number of slots (see k_pyramid).
     const int64_t share = (total + kXcds - 1) / kXcds;
-    int64_t slots = (int64_t)cus * resident_per_cu(k_pyramid) * slots_pct / (100 * kXcds);
+    int64_t slots = (int64_t)cus * resident_per_cu<k_pyramid>() * slots_pct / (100 * kXcds);
     slots = slots > share ? share : (slots < 1 ? 1 : slots);
     a.xcd_tiles = (int32_t)share;
     const int blocks = (int)(slots * kXcds);
     a.merge = blocks >= kMergeMinWgsPerImage * a.n;
+    note_pyramid_launch(blocks, a.merge);
     hipError_t e = launch_kernel("k_pyramid", k_pyramid, dim3(blocks), dim3(256), s, a);
     if (e != hipSuccess || a.g.L <= kFused)
         return e;
@@ -1793,7 +1796,7 @@ hipError_t launch_bytemaps(const BitmapArgs &a, int cus, hipStream_t s)
 {
     const int64_t total = a.chunk_start[a.g.L] * a.n;
     int64_t blocks = (total + 3) / 4;
-    const int64_t cap = (int64_t)cus * resident_per_cu(k_bytemaps);
+    const int64_t cap = (int64_t)cus * resident_per_cu<k_bytemaps>();
     blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
     return launch_kernel("k_bytemaps", k_bytemaps, dim3((unsigned)blocks), dim3(256), s, a);
 }
@@ -1802,7 +1805,7 @@ hipError_t launch_search_bytes(SearchArgs a, int cus, hipStream_t s)
 {
     const Geometry &g = a.g;
     a.coarse_n = 0;
-    const int64_t resident = (int64_t)cus * resident_per_cu(k_search_bytes);
+    const int64_t resident = (int64_t)cus * resident_per_cu<k_search_bytes>();
     for (int l = g.L - 1; l >= 0; --l) {
         const LevelGeom &lv = g.lv[l];
         const int units_x = (int)((lv.gray_pitch / 4 + kWave - 1) / kWave);
@@ -1827,7 +1830,7 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s, int block
 {
     const int64_t total = a.chunk_start[a.g.L] * a.n;
     int64_t blocks = (total + 3) / 4;
-    const int64_t cap = (int64_t)cus * resident_per_cu(k_bitmaps) * blocks_pct / 100;
+    const int64_t cap = (int64_t)cus * resident_per_cu<k_bitmaps>() * blocks_pct / 100;
     blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
     return launch_kernel("k_bitmaps", k_bitmaps, dim3((unsigned)blocks), dim3(256), s, a);
 }
@@ -1860,7 +1863,7 @@ int search_rows_rule(const Geometry &g, int l, int npairs, int cus)
     // compute unit holds about as many workgroups as it can run and none
     // waits for another to finish.
     static_assert(kRowsStep == kSearchBatch * kSearchDepth, "rows per stream fill whole batches");
-    const int64_t resident = (int64_t)cus * resident_per_cu(k_search_fine);
+    const int64_t resident = (int64_t)cus * resident_per_cu<k_search_fine>();
     int rows = kRowsStep;
     while (rows < kRowsMax && (int64_t)search_row_blocks(g, l, rows) * npairs > resident)
         rows += kRowsStep;

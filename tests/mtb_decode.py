@@ -44,11 +44,12 @@ def bitmaps(bm: np.ndarray, layout):
     return out
 
 
-def stack_workspace(ws: np.ndarray, ws_ptr: int, n: int, layout):
-    """Split an mtb_align_stack workspace into per-image (pyramid, bitmaps) byte arrays."""
-    start = (-ws_ptr) % 256
+def stack_workspace(mtb, ws, n: int, layout):
+    """Split an mtb_align_stack workspace (a device tensor) into per-image
+    (pyramid, bitmaps) byte arrays, at the places mtb_stack_image_buffers names."""
+    host = ws.cpu().numpy()
+    offs = mtb.mtb_stack_image_buffers(ws, n, layout.width, layout.height, layout.levels)
     P, B = layout.pyramid_bytes, layout.bitmaps_bytes
-    pyr = [ws[start + i * P:start + (i + 1) * P] for i in range(n)]
-    bm0 = start + n * P
-    bms = [ws[bm0 + i * B:bm0 + (i + 1) * B] for i in range(n)]
+    pyr = [host[p:p + P] for p, _ in offs]
+    bms = [host[b:b + B] for _, b in offs]
     return pyr, bms

@@ -239,7 +239,7 @@ def test_stack_intermediates_match_oracle(mtb):
     got, want = _check_stack(mtb, imgs, L)
     lay = mtb.mtb_get_layout(321, 203, L)
     ws = got["workspace"]
-    pyrs, bms = stack_workspace(ws.cpu().numpy(), ws.data_ptr(), 3, lay)
+    pyrs, bms = stack_workspace(mtb, ws, 3, lay)
     for i, p in enumerate(want["pyramids"]):
         for l, g in enumerate(gray_levels(pyrs[i], lay)):
             assert np.array_equal(g, p.gray(l))
@@ -259,8 +259,10 @@ def test_stack_histograms_many_workgroups_per_image(mtb, w, h, n):
     imgs, _, _ = synth.make_stack(w, h, n, 40, 700 + w + n, 20, sat_frac=0.05)
     L = 6
     got, want = _check_stack(mtb, imgs, L)
+    blocks, merged = mtb.mtb_test_last_pyramid()
+    assert merged == ((w, h) != (1300, 1100)), (blocks, merged)
     lay = mtb.mtb_get_layout(w, h, L)
-    pyrs, bms = stack_workspace(got["workspace"].cpu().numpy(), got["workspace"].data_ptr(), n, lay)
+    pyrs, bms = stack_workspace(mtb, got["workspace"], n, lay)
     for i, p in enumerate(want["pyramids"]):
         assert np.array_equal(histograms(pyrs[i], lay), p.hist), f"histograms of image {i}"
         assert np.array_equal(medians(bms[i], lay), p.median), f"medians of image {i}"
@@ -278,8 +280,8 @@ def test_repeated_runs_are_bit_identical(mtb):
     n = 5
     # Compare every defined byte of the pyramids and bitmaps (row padding and the
     # gaps between aligned planes hold no defined value).
-    pa, ba = stack_workspace(a["workspace"].cpu().numpy(), a["workspace"].data_ptr(), n, lay)
-    pb, bb = stack_workspace(b["workspace"].cpu().numpy(), b["workspace"].data_ptr(), n, lay)
+    pa, ba = stack_workspace(mtb, a["workspace"], n, lay)
+    pb, bb = stack_workspace(mtb, b["workspace"], n, lay)
     for i in range(n):
         for ga, gb in zip(gray_levels(pa[i], lay), gray_levels(pb[i], lay)):
             assert np.array_equal(ga, gb)
