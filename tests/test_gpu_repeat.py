@@ -76,3 +76,32 @@ def test_stack_tickets_repeated(mtb):
         assert torch.equal(shifts, f_shifts), f"shifts differ at run {k}"
         assert torch.equal(errs, f_errs), f"errors differ at run {k}"
         assert torch.equal(got["trace"], f_trace), f"trace differs at run {k}"
+
+
+@pytest.mark.timeout(600)
+def test_alternating_stacks_share_one_workspace(mtb):
+    """Two different stacks of one size alternate through the same workspace:
+    every call must give its own stack's results (shifts, errors, all nine
+    errors of every level), whatever the previous call left in the buffers
+    and in the caches of any XCD."""
+    w, h, L, n = 3000, 2000, 7, 5
+    ref = n // 2
+    want, dev = [], []
+    for seed in (11, 12):
+        imgs, _, _ = synth.make_stack(w, h, n, 200, seed, 40, sat_frac=0.03)
+        want.append(oracle.align_stack(imgs, L, ref_index=ref))
+        dev.append([torch.from_numpy(im).to(DEV) for im in imgs])
+    assert not np.array_equal(want[0]["shifts"], want[1]["shifts"])
+    ws = torch.empty(mtb.mtb_stack_workspace_bytes(n, w, h, L), dtype=torch.uint8, device=DEV)
+    out = torch.empty((n, 2), dtype=torch.int32, device=DEV)
+    errs = torch.empty(n, dtype=torch.int32, device=DEV)
+    for k in range(60):
+        s = k % 2
+        out.fill_(-99)
+        got = mtb.mtb_align_stack(dev[s], L, ref_index=ref, workspace=ws, trace=True, shifts=out, errs=errs)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want[s]["shifts"]), f"shifts of stack {s} at run {k}"
+        assert np.array_equal(errs.cpu().numpy().astype(np.int64), want[s]["errs"]), f"errors at run {k}"
+        tr = got["trace"].cpu().numpy().astype(np.int64)
+        for i, r in want[s]["pairs"].items():
+            assert np.array_equal(tr[i], r["trace"]), f"trace of image {i} of stack {s} at run {k}"
