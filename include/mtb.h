@@ -181,6 +181,26 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
                           uint32_t *d_trace, int32_t *d_level_shifts, void *stream);
 
 /*
+ * mtb_align_pair without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the search state (counters, bases,
+ * coarse surfaces, tickets; at most 10760 bytes, enough for MTB_MAX_LEVELS
+ * levels) lives in a static device array of the library, one per device,
+ * held until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); it clears the array with a kernel
+ * before the search.  Every call on a device shares that device's array and
+ * leaves its last contents there: calls that overlap on one device (on
+ * different streams or host threads) race and must be ordered by the caller.
+ * Arguments, results and errors as for mtb_align_pair, minus the workspace;
+ * MTB_ERR_WORKSPACE if the state of `levels` levels would not fit the array
+ * (never for valid levels), MTB_ERR_DEVICE if the array's address cannot be
+ * obtained.
+ */
+mtb_status mtb_align_pair_scratch(const void *d_bm_ref, const void *d_bm_mov, int32_t width,
+                                  int32_t height, int32_t levels, int32_t *d_shift, uint32_t *d_err,
+                                  uint32_t *d_trace, int32_t *d_level_shifts, void *stream);
+
+/*
  * Whole-stack alignment (Section III-B: every image is uploaded once, its
  * pyramid and bitmaps computed once, and the stack aligned pairwise).  Every
  * image is aligned against the reference image; each image's pyramid,

@@ -34,6 +34,7 @@ __all__ = [
     "mtb_build_pyramid",
     "mtb_bitmaps",
     "mtb_align_pair",
+    "mtb_align_pair_scratch",
     "mtb_align_stack",
     "mtb_align_stack_chained",
     "mtb_align_stack_bytemaps",
@@ -178,6 +179,8 @@ def lib():
     L.mtb_bitmaps.argtypes = [P, i32, i32, i32, i32, P, sz, P]
     L.mtb_bitmaps.restype = ctypes.c_int
     L.mtb_align_pair.argtypes = [P, P, i32, i32, i32, P, sz, P, P, P, P, P]
+    L.mtb_align_pair_scratch.argtypes = [P, P, i32, i32, i32, P, P, P, P, P]
+    L.mtb_align_pair_scratch.restype = ctypes.c_int
     L.mtb_align_pair.restype = ctypes.c_int
     L.mtb_align_stack.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, i32, i32, P, sz, P, P, P, P]
     L.mtb_align_stack.restype = ctypes.c_int
@@ -339,6 +342,23 @@ def mtb_align_pair(bm_ref: torch.Tensor, bm_mov: torch.Tensor, width: int, heigh
                                 workspace.numel(), _ptr(shift), _ptr(err), _ptr(tr), _ptr(ls),
                                 _stream(stream)))
     return {"shift": shift, "err": err, "trace": tr, "level_shifts": ls}
+
+
+def mtb_align_pair_scratch(bm_ref: torch.Tensor, bm_mov: torch.Tensor, width: int, height: int,
+                           levels: int, shift: torch.Tensor, err: torch.Tensor, trace: torch.Tensor | None = None,
+                           level_shifts: torch.Tensor | None = None, stream=None) -> dict:
+    """mtb_align_pair with the search state in the library's static device array
+    (no workspace; the caller passes every output, so nothing is allocated here)."""
+    _device_u8(bm_ref, "bm_ref")
+    _device_u8(bm_mov, "bm_mov")
+    for t, n, what in ((shift, 2, "shift"), (err, 1, "err"), (trace, 9 * levels, "trace"),
+                       (level_shifts, 2 * levels, "level_shifts")):
+        if t is not None and (t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < n):
+            raise ValueError(f"{what}: a contiguous int32 tensor of at least {n} elements")
+    _check("mtb_align_pair_scratch",
+           lib().mtb_align_pair_scratch(_ptr(bm_ref), _ptr(bm_mov), width, height, levels, _ptr(shift), _ptr(err),
+                                        _ptr(trace), _ptr(level_shifts), _stream(stream)))
+    return {"shift": shift, "err": err, "trace": trace, "level_shifts": level_shifts}
 
 
 def mtb_align_stack_chained(images, levels: int, exclude_range: int = 4, ref_index: int = -1,

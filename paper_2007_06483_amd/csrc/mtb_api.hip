@@ -348,6 +348,78 @@ void quadrant_items(const uint8_t *ref, const uint8_t *mov, int32_t W, int32_t H
     }
 }
 
+// One pair's search (counters, bases, coarse surfaces, tickets) in the device
+// buffer `state`, which is cleared first.
+mtb_status align_pair_in(const void *d_bm_ref, const void *d_bm_mov, const Geometry &g, uint32_t *state,
+                         int32_t *d_shift, uint32_t *d_err, uint32_t *d_trace, int32_t *d_level_shifts, int cus,
+                         hipStream_t s)
+{
+    const int levels = g.L;
+
+    ZeroArgs z;
+    memset(&z, 0, sizeof(z));
+    z.ptr[0] = state;
+    z.words[0] = state_stride_words(levels) + kTicketWords;  // counters, bases, surfaces, tickets
+    z.count = 1;
+    if (launch_zero(z, s) != hipSuccess)
+        return MTB_ERR_DEVICE;
+
+    SearchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ref[0] = (const uint8_t *)d_bm_ref;
+    a.mov[0] = (const uint8_t *)d_bm_mov;
+    a.state = state;
+    a.done = state + state_stride_words(levels);
+    a.state_stride = state_stride_words(levels);
+    a.npairs = 1;
+    a.out.pair_image[0] = 0;
+    a.out.n_out = 1;
+    a.out.shifts = d_shift;
+    a.out.errs = d_err;
+    a.out.trace = d_trace;
+    a.out.level_shifts = d_level_shifts;
+    a.g = g;
+    return device_status(launch_search(a, cus, s));
+}
+
+// ---- the allocation-free pair search (mtb_align_pair_scratch)
+
+// One pair's search state and tickets for the most levels a call takes.
+constexpr int64_t kPairScratchWords =
+    (((int64_t)kMaxLevels * kCounterWords + 2 * kMaxLevels + kSurfWords + kAlign / 4 - 1) / (kAlign / 4)) *
+        (kAlign / 4) +
+    kTicketWords;
+
+}  // namespace
+
+// The search state of mtb_align_pair_scratch: one copy per device, held until
+// the process ends, shared by every call on that device (calls that overlap
+// on one device race on it).  Host code never passes this name to a kernel:
+// it is a host-side stand-in; device_scratch() gives the device address.
+static __device__ __align__(256) uint32_t scratch[kPairScratchWords];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+uint32_t *g_scratch_ptr[64];
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current; null if the lookup fails.
+uint32_t *device_scratch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return nullptr;
+        g_scratch_ptr[dev] = (uint32_t *)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 void note_pyramid_launch(int blocks, int merged)
@@ -537,33 +609,28 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
     const int cus = current_device_cus();
     if (cus <= 0)
         return MTB_ERR_UNSUPPORTED;
-    hipStream_t s = (hipStream_t)stream;
-    uint32_t *state = (uint32_t *)d_workspace;
+    return align_pair_in(d_bm_ref, d_bm_mov, g, (uint32_t *)d_workspace, d_shift, d_err, d_trace, d_level_shifts,
+                         cus, (hipStream_t)stream);
+}
 
-    ZeroArgs z;
-    memset(&z, 0, sizeof(z));
-    z.ptr[0] = state;
-    z.words[0] = state_stride_words(levels) + kTicketWords;  // counters, bases, surfaces, tickets
-    z.count = 1;
-    if (launch_zero(z, s) != hipSuccess)
+mtb_status mtb_align_pair_scratch(const void *d_bm_ref, const void *d_bm_mov, int32_t width,
+                                  int32_t height, int32_t levels, int32_t *d_shift, uint32_t *d_err,
+                                  uint32_t *d_trace, int32_t *d_level_shifts, void *stream)
+{
+    Geometry g;
+    if (!d_bm_ref || !d_bm_mov || !d_shift || !d_err || !make_geometry(width, height, levels, &g))
+        return MTB_ERR_INVALID_ARG;
+    // The array holds the state of MTB_MAX_LEVELS levels, the most any call takes.
+    if (state_stride_words(levels) + kTicketWords > kPairScratchWords)
+        return MTB_ERR_WORKSPACE;
+    const int cus = current_device_cus();
+    if (cus <= 0)
+        return MTB_ERR_UNSUPPORTED;
+    uint32_t *state = device_scratch();
+    if (!state)
         return MTB_ERR_DEVICE;
-
-    SearchArgs a;
-    memset(&a, 0, sizeof(a));
-    a.ref[0] = (const uint8_t *)d_bm_ref;
-    a.mov[0] = (const uint8_t *)d_bm_mov;
-    a.state = state;
-    a.done = state + state_stride_words(levels);
-    a.state_stride = state_stride_words(levels);
-    a.npairs = 1;
-    a.out.pair_image[0] = 0;
-    a.out.n_out = 1;
-    a.out.shifts = d_shift;
-    a.out.errs = d_err;
-    a.out.trace = d_trace;
-    a.out.level_shifts = d_level_shifts;
-    a.g = g;
-    return device_status(launch_search(a, cus, s));
+    return align_pair_in(d_bm_ref, d_bm_mov, g, state, d_shift, d_err, d_trace, d_level_shifts, cus,
+                         (hipStream_t)stream);
 }
 
 }  // extern "C"
