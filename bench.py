@@ -222,6 +222,13 @@ def run_batch(args, mtb, synth, torch, np, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3 / steps
 
+    tuned_keys = None
+    if args.tune:
+        # The library's tuner picks every group key's shape once, before timing.
+        tuned_keys = mtb.mtb_tune_batch(pairs, workspace=ws, shifts=shifts, errs=errs)
+        log(f"tuned {tuned_keys} group shapes")
+        save_tune_cache(args, mtb)
+
     # Timed region of the headline number: K batched calls, k_pyramid bracketed by events.
     for _ in range(args.warmup):
         batched()
@@ -272,6 +279,8 @@ def run_batch(args, mtb, synth, torch, np, dev):
         "graph_replay": {"ms_per_step": round(ms_graph, 4), "MPps": round(mp_total / (ms_graph / 1e3), 1)},
         "plain_per_pair": {"ms_per_step": round(ms_plain, 4), "MPps": round(mp_total / (ms_plain / 1e3), 1),
                            "same_results": same},
+        "batched_vs_plain": round(ms_plain / ms_batched, 3),
+        "launch_shapes": {"tuned_group_keys": tuned_keys, "cache": args.tune_cache},
     }
     if not args.no_cpu_baseline:
         # The whole batch on the CPU oracle: pairs spread over the host cores.
@@ -422,6 +431,37 @@ def run_quadrants(args, mtb, synth, torch, np, dev):
     print(json.dumps(result), flush=True)
 
 
+def save_tune_cache(args, mtb):
+    if args.tune_cache:
+        mtb.mtb_tune_save(args.tune_cache)
+        log(f"launch shapes saved to {args.tune_cache}")
+
+
+def tune_served_buckets(mtb, synth, base_dev, BW, BH):
+    """Tunes one stack per (images, half-octave size bucket) of the served mix
+    (3-9 images of 1-48 MP at 3:2), cut from the resident base scene; requests
+    without a shape of their own use their bucket's."""
+    import math
+
+    lo, hi = math.ceil(2 * math.log2(1e6)), math.floor(2 * math.log2(48e6))
+    count = 0
+    for n in range(3, 10):
+        for b in range(lo, hi + 1):
+            px = 2.0 ** (b / 2)
+            W = int(round(math.sqrt(px * 1.5)))
+            H = int(round(W / 1.5))
+            L = synth.serve_levels(W, H)
+            R = 1 << (L - 1)
+            W, H = min(W, BW - 2 * R), min(H, BH - 2 * R)
+            L = synth.serve_levels(W, H)
+            spec = {"offsets": [(0, 0)] * n, "x0": R, "y0": R, "width": W, "height": H,
+                    "exposures": [4 + i - n // 2 for i in range(n)]}
+            imgs = [synth.serve_crop(base_dev, spec, i) for i in range(n)]
+            mtb.mtb_tune_stack(imgs, L)
+            count += 1
+    return count
+
+
 def run_served(args, mtb, synth, torch, np, dev):
     """Poisson arrivals of exposure stacks served with continuous batching.
 
@@ -439,7 +479,7 @@ def run_served(args, mtb, synth, torch, np, dev):
     base_host = [torch.from_numpy(b).pin_memory() for b in base] if args.serve_host_seconds > 0 else None
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
-    def requests(seed, rate, seconds, host):
+    def requests(seed, rate, seconds, host, plain=False):
         specs = synth.serve_requests(seed, rate, seconds, BW, BH)
         src = base_host if host else base_dev
         out = []
@@ -447,7 +487,7 @@ def run_served(args, mtb, synth, torch, np, dev):
             imgs = [synth.serve_crop(src, r, i) for i in range(r["n"])]
             out.append(Request(rid=r["rid"], arrival=r["arrival"], images=imgs, levels=r["levels"],
                                workspace_bytes=footprint_bytes(mtb, r["n"], r["width"], r["height"],
-                                                               r["levels"], host),
+                                                               r["levels"], host, plain),
                                megapixels=r["n"] * r["width"] * r["height"] / 1e6))
         return out
 
@@ -455,12 +495,19 @@ def run_served(args, mtb, synth, torch, np, dev):
     pool_bytes = 24 << 30
     pool = torch.empty(pool_bytes, dtype=torch.uint8, device=dev)
     execute, poll = gpu_executor(pool, slots)
+    execute_plain, poll_plain = gpu_executor(pool, slots, plain=True)
+
+    tuned = None
+    if args.tune:
+        tuned = tune_served_buckets(mtb, synth, base_dev, BW, BH)
+        log(f"tuned {tuned} size-bucket shapes")
+        save_tune_cache(args, mtb)
 
     kept = {}
 
-    def serve(rate, seconds, seed, host=False, keep=False):
-        reqs = requests(seed, rate, seconds, host)
-        srv = Server(pool_bytes, slots, execute, poll)
+    def serve(rate, seconds, seed, host=False, keep=False, plain=False):
+        reqs = requests(seed, rate, seconds, host, plain)
+        srv = Server(pool_bytes, slots, execute_plain if plain else execute, poll_plain if plain else poll)
         t_run = time.perf_counter()
         res = srv.run(reqs)
         torch.cuda.synchronize()
@@ -515,6 +562,17 @@ def run_served(args, mtb, synth, torch, np, dev):
     for rate in (800.0, 1600.0, 3200.0, 6400.0, 12800.0):
         sweep.append(serve(rate, 3.0, 50 + int(rate)))
         log(json.dumps(sweep[-1]))
+    # The same request traces through plain per-call alignment (mtb_build_pyramid
+    # and mtb_bitmaps per image, mtb_align_pair per moving image) on the same
+    # slots and pool, for comparison with the one-call-per-stack path.
+    serve(200.0, 0.5, 99, plain=True)  # warm-up
+    log(f"plain per-call path: serving Poisson(200/s) for {args.serve_plain_seconds:.0f} s ...")
+    plain_run = serve(200.0, args.serve_plain_seconds, 5, plain=True)
+    log(json.dumps(plain_run))
+    plain_sweep = []
+    for rate in (3200.0, 6400.0, 12800.0):
+        plain_sweep.append(serve(rate, 3.0, 50 + int(rate), plain=True))
+        log(json.dumps(plain_sweep[-1]))
     host_run, host_sweep = None, []
     if base_host is not None:
         serve(200.0, 0.5, 98, host=True)  # warm-up
@@ -543,6 +601,11 @@ def run_served(args, mtb, synth, torch, np, dev):
         "latency_ms": {"p50": main_run["p50_ms"], "p99": main_run["p99_ms"]},
         "served": main_run,
         "saturation_sweep": sweep,
+        "plain_per_call": {"path": "mtb_build_pyramid + mtb_bitmaps per image, mtb_align_pair per moving image",
+                           "served": plain_run, "saturation_sweep": plain_sweep},
+        "stack_vs_plain_saturation_MPps": round(max(r["MPps"] for r in sweep) /
+                                                max(r["MPps"] for r in plain_sweep), 3),
+        "launch_shapes": {"tuned_size_buckets": tuned, "cache": args.tune_cache},
         "host_staged": {"staging": "host (pinned base, mtb_stage_rgb per image inside each request)",
                         "served": host_run, "saturation_sweep": host_sweep},
     }
@@ -564,6 +627,10 @@ def main():
                              "served_poisson200", "apply7_6000x4000", "quadrants7_6000x4000"])
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
     ap.add_argument("--serve-slots", type=int, default=8, help="served mode: stacks in flight at most")
+    ap.add_argument("--serve-plain-seconds", type=float, default=20.0,
+                    help="served mode: length of the plain per-call comparison run")
+    ap.add_argument("--tune-cache", default=None,
+                    help="launch-shape file: loaded before timing if it exists; written after --tune")
     ap.add_argument("--serve-host-seconds", type=float, default=20.0,
                     help="served mode: length of the host-staged run (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -600,6 +667,8 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     mtb.lib()  # raises if libmtb.so is not built
     dev = torch.device("cuda:0")
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        log(f"launch shapes loaded from {args.tune_cache}: {mtb.mtb_tune_load(args.tune_cache)}")
 
     if args.workload == "batch64_uneven":
         return run_batch(args, mtb, synth, torch, np, dev)
@@ -643,8 +712,8 @@ def main():
     # rocprofv3 summaries (the tuner's trial launches would mix into them).
     shape = None
     if args.shape and not bytemaps:
-        full = {"pyramid_slots_pct": 100, "bitmaps_blocks_pct": 100, "search_rows": [], "overlap": 1,
-                "bitmaps0_blocks_pct": 67}
+        full = {"pyramid_slots_pct": 100, "pyramid_tile_group": 1, "bitmaps_blocks_pct": 100, "bitmaps_waves": 4,
+                "coarse_levels": -1, "search_rows": [], "search_lanes": []}
         full.update(json.loads(args.shape))
         mtb.mtb_set_shape(n, W, H, int(d_imgs[0].stride(0)), L, full)
         shape = dict(mtb.mtb_tuned_shape(n, W, H, int(d_imgs[0].stride(0)), L), step_ms=0.0, default_ms=0.0)
@@ -652,6 +721,7 @@ def main():
     if not bytemaps and args.tune:
         shape = mtb.mtb_tune_stack(d_imgs, L, ref_index=ref, workspace=ws, shifts=shifts, errs=errs)
         log(f"launch shape: {json.dumps(shape)}")
+        save_tune_cache(args, mtb)
     torch.cuda.synchronize()
 
     # Timed region: K whole-stack alignments; in every --event-every-th step
@@ -773,12 +843,14 @@ def main():
         "step_us": {"median": round(step_us[len(step_us) // 2], 1), "min": round(step_us[0], 1),
                     "max": round(step_us[-1], 1), "steps": len(step_us)},
         "e2e_incl_h2d": {"ms_per_step": round(e2e_ms, 3), "MPps": round(mp_total / (e2e_ms / 1e3), 1)},
-        "launch_shape": {"tuned": False, "pyramid_slots_pct": 100, "bitmaps_blocks_pct": 100,
-                         "search_rows": "built-in rule", "overlap": 1, "bitmaps0_blocks_pct": 67}
+        "launch_shape": {"tuned": False, "pyramid_slots_pct": 100, "pyramid_tile_group": 1,
+                         "bitmaps_blocks_pct": 100, "bitmaps_waves": 4, "coarse_levels": "built-in rule",
+                         "search_rows": "built-in rule", "search_lanes": "built-in rule"}
         if shape is None else {
             "tuned": bool(args.tune), "pyramid_slots_pct": shape["pyramid_slots_pct"],
-            "bitmaps_blocks_pct": shape["bitmaps_blocks_pct"], "search_rows": shape["search_rows"][:L],
-            "overlap": shape["overlap"], "bitmaps0_blocks_pct": shape["bitmaps0_blocks_pct"],
+            "pyramid_tile_group": shape["pyramid_tile_group"], "bitmaps_blocks_pct": shape["bitmaps_blocks_pct"],
+            "bitmaps_waves": shape["bitmaps_waves"], "coarse_levels": shape["coarse_levels"],
+            "search_rows": shape["search_rows"][:L], "search_lanes": shape["search_lanes"][:L],
             "tuner_step_ms": round(shape["step_ms"], 4), "tuner_default_ms": round(shape["default_ms"], 4)},
     }
 

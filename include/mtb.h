@@ -254,38 +254,53 @@ mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int
                                    uint32_t *d_trace, void *stream);
 
 /*
- * Launch shapes and their tuner.  How a stack alignment is cut into
- * workgroups never changes its results (every shape gives the same bits);
- * it changes its speed, and the best shape depends on the image size and
- * count.  A shape: k_pyramid and k_bitmaps workgroups as a percentage of one
- * round of the workgroups the device holds at once, and the rows each row
- * stream of k_search_fine covers at every level (0: the built-in rule, the
- * fewest rows that keep one level's grid within one resident round).
- * Shapes are kept per (n, width, height, levels, whether row_stride is a
- * multiple of 16, else of 4, else neither) in
- * a process-wide table guarded by a mutex; mtb_align_stack and
- * mtb_align_stack_chained use the table's shape for their key, the built-in
- * shape otherwise.
+ * Launch shapes and their tuner.  How an alignment is cut into workgroups
+ * never changes its results (every shape gives the same bits); it changes
+ * its speed, and the best shape depends on the image size and count.  A
+ * shape (mtb_launch_shape) fixes:
+ *   - the pyramid pass: workgroups as a percentage of one round of the
+ *     workgroups the device holds at once, and how many horizontally
+ *     adjacent 64x256 tiles a workgroup takes at a time (1, 2 or 4);
+ *   - the bitmaps pass: workgroups as a percentage of one resident round, and
+ *     wavefronts per workgroup (2, 4 or 8);
+ *   - the search: how many of the coarsest levels are searched over
+ *     exhaustive windows (-1: the built-in rule; 0..3; the results are the
+ *     same either way), and per fine level the rows each row stream covers
+ *     and the lanes of a row stream (8, 16, 32 or 64; 0: the built-in rules,
+ *     the fewest rows that keep one level's grid within one resident round
+ *     and the width that pads rows least).
+ * Shapes are kept per key (n images, width, height, levels, and whether
+ * row_stride is a multiple of 16, else of 4, else neither) in a process-wide
+ * table guarded by a mutex.  A key without a shape of its own uses the shape
+ * last stored for its bucket: same n, levels and row-stride class, and a
+ * pixel count in the same half octave (round(2 log2(width * height))).
+ * mtb_align_stack, mtb_align_stack_chained and, per group of equal items,
+ * mtb_align_batch and mtb_align_quadrants use the table's shape, the
+ * built-in shape otherwise.
  */
 typedef struct mtb_launch_shape {
     int32_t pyramid_slots_pct;  /* 25 .. 400 (default 100) */
+    int32_t pyramid_tile_group; /* 1, 2 or 4 (default 1) */
     int32_t bitmaps_blocks_pct; /* 25 .. 100 (default 100) */
+    int32_t bitmaps_waves;      /* 2, 4 or 8 (default 4) */
+    int32_t coarse_levels;      /* -1 (rule), 0 .. 3 */
     int32_t search_rows[16];    /* per level: 0, or a multiple of 4 in 4 .. 64 */
-    float step_ms;              /* mtb_tune_stack: median time of one call with this shape */
-    float default_ms;           /* mtb_tune_stack: the same with the built-in shape */
+    int32_t search_lanes[16];   /* per level: 0, 8, 16, 32 or 64 */
+    float step_ms;              /* tuners: median time of one call with this shape */
+    float default_ms;           /* tuners: the same with the built-in shape */
 } mtb_launch_shape;
 
 /*
  * Tunes the launch shape of mtb_align_stack for these images: times whole
  * alignments (median of 7 after a warm-up, HIP events on `stream`) under the
  * built-in shape and under candidates changed one knob at a time (pyramid
- * 50/75/150/200 %, bitmaps 50/75 %, each fine level's rows halved or
- * doubled), keeps a change only if it is at least 2 % faster, stores the
- * result in the table and writes it to *h_out.  Arguments as for
- * mtb_align_stack; d_shifts and d_errs hold the alignment's results when it
- * returns.  Waits for the device (not capturable in a HIP graph); allocates
- * no device memory.
- * Errors: as mtb_align_stack; MTB_ERR_INVALID_ARG for a null h_out.
+ * 50/75/150/200 %, tile groups of 2 and 4, bitmaps 50/75 %, 2 and 8
+ * wavefronts, one coarse level fewer or more, and at each fine level every
+ * stream width and the rows halved or doubled), keeps a change only if it is
+ * at least 2 % faster, stores the result in the table and writes it to
+ * *h_out.  Arguments as for mtb_align_stack; d_shifts and d_errs receive the
+ * results of the last call (identical under every shape).
+ * Errors: as mtb_align_stack, MTB_ERR_INVALID_ARG for a null h_out.
  */
 mtb_status mtb_tune_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
                           int64_t row_stride, int32_t levels, int32_t exclude_range, int32_t ref_index,
@@ -304,6 +319,24 @@ mtb_status mtb_tuned_shape(int32_t n, int32_t width, int32_t height, int64_t row
 
 /* Forgets every stored shape. */
 void mtb_tune_reset(void);
+
+/*
+ * Writes every stored shape to the text file `path`, under a first line that
+ * names the current device's architecture and the HIP runtime version.
+ * Errors: MTB_ERR_INVALID_ARG (null path, file not writable),
+ *         MTB_ERR_UNSUPPORTED (no device to name).
+ */
+mtb_status mtb_tune_save(const char *path);
+
+/*
+ * Stores the shapes of a file written by mtb_tune_save, if its first line
+ * names the current device's architecture and HIP runtime version (shapes
+ * tuned elsewhere are skipped whole: *h_loaded = 0); *h_loaded receives the
+ * number stored.  The file is read completely before anything is stored.
+ * Errors: MTB_ERR_INVALID_ARG (null pointer, unreadable or malformed file,
+ *         a shape out of range), MTB_ERR_UNSUPPORTED (no device).
+ */
+mtb_status mtb_tune_load(const char *path, int32_t *h_loaded);
 
 /*
  * For tests of error handling (callers that must survive a failed launch):
@@ -388,8 +421,9 @@ size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items)
  * pairwise alignment of Section III-A (as mtb_align_pair on the items' own
  * pyramids and bitmaps, built as in mtb_build_pyramid and mtb_bitmaps).
  * Items of equal width, height, row stride and level count are processed
- * together, up to 16 pairs (32 images) per launch of each pass; the groups run
- * one after another on `stream`, reusing the workspace.  The call enqueues a
+ * together, up to 16 pairs (32 images) per launch of each pass, with the
+ * launch shape the table holds for the group's key; the groups run one after
+ * another on `stream`, reusing the workspace.  The call enqueues a
  * fixed sequence of kernels (no host synchronisation, no memset), so it can be
  * captured in a HIP graph and replayed.
  *   h_items          host array of n_items items (1 .. MTB_MAX_BATCH)
@@ -402,6 +436,21 @@ size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items)
 mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range,
                            void *d_workspace, size_t workspace_bytes, int32_t *d_shifts,
                            uint32_t *d_errs, void *stream);
+
+/*
+ * Tunes the launch shapes of a batch: for each distinct group key (2 x pairs
+ * of the group, width, height, levels, row-stride class; see the launch
+ * shapes above), in order of first appearance, times the whole batch under
+ * the candidate shapes of mtb_tune_stack for that key (the other keys at
+ * their current shapes) and stores the winner in the table; *h_tuned
+ * receives the number of keys tuned.  Arguments as for mtb_align_batch;
+ * d_shifts and d_errs receive the results of a last call with the tuned
+ * shapes (identical under every shape).
+ * Errors: as mtb_align_batch, MTB_ERR_INVALID_ARG for a null h_tuned.
+ */
+mtb_status mtb_tune_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range,
+                          void *d_workspace, size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                          void *stream, int32_t *h_tuned);
 
 /*
  * Quadrant check for rotation (Section II: to find out whether a pair needs

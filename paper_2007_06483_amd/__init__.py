@@ -45,6 +45,9 @@ __all__ = [
     "mtb_set_shape",
     "mtb_tuned_shape",
     "mtb_tune_reset",
+    "mtb_tune_save",
+    "mtb_tune_load",
+    "mtb_tune_batch",
     "mtb_test_fail_launch",
     "mtb_test_last_pyramid",
     "mtb_stack_image_buffers",
@@ -113,20 +116,32 @@ class _KernelTime(ctypes.Structure):
 
 
 class _LaunchShape(ctypes.Structure):
-    _fields_ = [("pyramid_slots_pct", ctypes.c_int32), ("bitmaps_blocks_pct", ctypes.c_int32),
-                ("search_rows", ctypes.c_int32 * MTB_MAX_LEVELS), ("step_ms", ctypes.c_float),
+    _fields_ = [("pyramid_slots_pct", ctypes.c_int32), ("pyramid_tile_group", ctypes.c_int32),
+                ("bitmaps_blocks_pct", ctypes.c_int32), ("bitmaps_waves", ctypes.c_int32),
+                ("coarse_levels", ctypes.c_int32), ("search_rows", ctypes.c_int32 * MTB_MAX_LEVELS),
+                ("search_lanes", ctypes.c_int32 * MTB_MAX_LEVELS), ("step_ms", ctypes.c_float),
                 ("default_ms", ctypes.c_float)]
 
 
+_SHAPE_DEFAULTS = {"pyramid_slots_pct": 100, "pyramid_tile_group": 1, "bitmaps_blocks_pct": 100,
+                   "bitmaps_waves": 4, "coarse_levels": -1}
+
+
 def _shape_dict(c: _LaunchShape) -> dict:
-    return {"pyramid_slots_pct": c.pyramid_slots_pct, "bitmaps_blocks_pct": c.bitmaps_blocks_pct,
-            "search_rows": list(c.search_rows), "step_ms": float(c.step_ms), "default_ms": float(c.default_ms)}
+    d = {k: int(getattr(c, k)) for k in _SHAPE_DEFAULTS}
+    d.update({"search_rows": list(c.search_rows), "search_lanes": list(c.search_lanes),
+              "step_ms": float(c.step_ms), "default_ms": float(c.default_ms)})
+    return d
 
 
 def _shape_struct(d: dict) -> _LaunchShape:
     rows = list(d.get("search_rows", [])) + [0] * MTB_MAX_LEVELS
-    return _LaunchShape(int(d.get("pyramid_slots_pct", 100)), int(d.get("bitmaps_blocks_pct", 100)),
-                        (ctypes.c_int32 * MTB_MAX_LEVELS)(*rows[:MTB_MAX_LEVELS]), 0.0, 0.0)
+    lanes = list(d.get("search_lanes", [])) + [0] * MTB_MAX_LEVELS
+    v = {k: int(d.get(k, dv)) for k, dv in _SHAPE_DEFAULTS.items()}
+    return _LaunchShape(v["pyramid_slots_pct"], v["pyramid_tile_group"], v["bitmaps_blocks_pct"],
+                        v["bitmaps_waves"], v["coarse_levels"],
+                        (ctypes.c_int32 * MTB_MAX_LEVELS)(*rows[:MTB_MAX_LEVELS]),
+                        (ctypes.c_int32 * MTB_MAX_LEVELS)(*lanes[:MTB_MAX_LEVELS]), 0.0, 0.0)
 
 
 class Layout:
@@ -205,6 +220,10 @@ def lib():
     L.mtb_tuned_shape.restype = ctypes.c_int
     L.mtb_tune_reset.argtypes = []
     L.mtb_tune_reset.restype = None
+    L.mtb_tune_save.argtypes = [ctypes.c_char_p]
+    L.mtb_tune_save.restype = ctypes.c_int
+    L.mtb_tune_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]
+    L.mtb_tune_load.restype = ctypes.c_int
     L.mtb_test_fail_launch.argtypes = [i32]
     L.mtb_test_fail_launch.restype = ctypes.c_int
     L.mtb_test_last_pyramid.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -216,6 +235,8 @@ def lib():
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
     L.mtb_batch_workspace_bytes.restype = sz
     L.mtb_align_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P]
+    L.mtb_tune_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P, ctypes.POINTER(i32)]
+    L.mtb_tune_batch.restype = ctypes.c_int
     L.mtb_align_batch.restype = ctypes.c_int
     L.mtb_profile_pause.argtypes = [i32]
     L.mtb_profile_pause.restype = ctypes.c_int
@@ -461,6 +482,19 @@ def mtb_tune_reset() -> None:
     lib().mtb_tune_reset()
 
 
+def mtb_tune_save(path: str) -> None:
+    """Write every stored launch shape (with the device architecture and HIP version) to ``path``."""
+    _check("mtb_tune_save", lib().mtb_tune_save(os.fsencode(path)))
+
+
+def mtb_tune_load(path: str) -> int:
+    """Store the shapes of a file written by mtb_tune_save on this architecture and HIP
+    version; returns how many were stored (0 for a file from another platform)."""
+    n = ctypes.c_int32(0)
+    _check("mtb_tune_load", lib().mtb_tune_load(os.fsencode(path), ctypes.byref(n)))
+    return int(n.value)
+
+
 def mtb_test_fail_launch(after: int) -> None:
     """Make this thread's launch after `after` successful ones fail, once (tests only)."""
     _check("mtb_test_fail_launch", lib().mtb_test_fail_launch(int(after)))
@@ -597,6 +631,26 @@ def mtb_align_batch(pairs, exclude_range: int = 4, workspace: torch.Tensor | Non
            lib().mtb_align_batch(items, n, exclude_range, _ptr(workspace), workspace.numel(),
                                  _ptr(shifts), _ptr(errs), _stream(stream)))
     return {"shifts": shifts, "errs": errs, "workspace": workspace}
+
+
+def mtb_tune_batch(pairs, exclude_range: int = 4, workspace: torch.Tensor | None = None,
+                   shifts=None, errs=None, stream=None) -> int:
+    """Tune and store the launch shape of every group key of a batch (see mtb_align_batch);
+    returns the number of keys tuned.  shifts/errs (if given) receive the batch's results."""
+    items = _batch_items(pairs)
+    n = len(pairs)
+    dev = pairs[0][0].device
+    need = int(lib().mtb_batch_workspace_bytes(items, n))
+    workspace = _buffer(max(need, 1), dev, workspace)
+    if shifts is None:
+        shifts = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    if errs is None:
+        errs = torch.empty(n, dtype=torch.int32, device=dev)
+    tuned = ctypes.c_int32(0)
+    _check("mtb_tune_batch",
+           lib().mtb_tune_batch(items, n, exclude_range, _ptr(workspace), workspace.numel(), _ptr(shifts),
+                                _ptr(errs), _stream(stream), ctypes.byref(tuned)))
+    return int(tuned.value)
 
 
 def mtb_profile_begin(kernel_name: str | None = None) -> None:

@@ -3,9 +3,12 @@
 // allocated here; every buffer comes from the caller.
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
+#include <stdio.h>
 #include <string.h>
+#include <string>
 #include <vector>
 
 #include "mtb_internal.h"
@@ -186,7 +189,7 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     pa.n = n;
     pa.align = align;
     pa.g = g;
-    e = launch_pyramid(pa, cus, s, t.pyr_pct);
+    e = launch_pyramid(pa, cus, s, t.pyr_pct, t.pyr_group_log2);
     if (e != hipSuccess)
         return e;
 
@@ -200,7 +203,7 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     ba.exclude = exclude;
     ba.g = g;
     fill_chunk_starts(g, ba.chunk_start);
-    e = bytemaps ? launch_bytemaps(ba, cus, s) : launch_bitmaps(ba, cus, s, t.bm_pct);
+    e = bytemaps ? launch_bytemaps(ba, cus, s) : launch_bitmaps(ba, cus, s, t.bm_pct, t.bm_waves);
     if (e != hipSuccess || npairs == 0)
         return e;
 
@@ -217,11 +220,14 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     sa.npairs = npairs;
     sa.out = out;
     sa.g = g;
-    return bytemaps ? launch_search_bytes(sa, cus, s) : launch_search(sa, cus, s, t.rows);
+    return bytemaps ? launch_search_bytes(sa, cus, s) : launch_search(sa, cus, s, &t);
 }
 
-// Tuned launch shapes of stack alignments, per (images, size, levels, row
-// alignment); filled by mtb_tune_stack / mtb_set_shape, read by align_stack.
+// Tuned launch shapes, per (images, size, levels, row alignment); filled by
+// mtb_tune_stack, mtb_tune_batch, mtb_set_shape and mtb_tune_load, read by the
+// stack and batch calls.  A shape also serves, until one of their own is
+// stored, the sizes of its bucket: same images, levels and row alignment, and
+// a pixel count in the same half octave.
 struct TuneKey {
     int n, w, h, levels, align;
     bool operator<(const TuneKey &o) const
@@ -229,17 +235,41 @@ struct TuneKey {
         return n != o.n ? n < o.n : w != o.w ? w < o.w : h != o.h ? h < o.h : levels != o.levels ? levels < o.levels
                                                                                                   : align < o.align;
     }
+    bool operator==(const TuneKey &o) const
+    {
+        return n == o.n && w == o.w && h == o.h && levels == o.levels && align == o.align;
+    }
+};
+struct BucketKey {
+    int n, levels, align, bucket;
+    bool operator<(const BucketKey &o) const
+    {
+        return n != o.n ? n < o.n : levels != o.levels ? levels < o.levels : align != o.align ? align < o.align
+                                                                                             : bucket < o.bucket;
+    }
 };
 std::mutex g_tune_mutex;
 std::map<TuneKey, LaunchTune> g_tune_table;
+std::map<BucketKey, LaunchTune> g_bucket_table;
 
+BucketKey bucket_of(const TuneKey &k)
+{
+    return BucketKey{k.n, k.levels, k.align, (int)std::lround(2.0 * std::log2((double)k.w * k.h))};
+}
+
+// The shape for key k: its own, else its bucket's; false if neither exists.
 bool tune_lookup(const TuneKey &k, LaunchTune *t)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     const auto it = g_tune_table.find(k);
-    if (it == g_tune_table.end())
+    if (it != g_tune_table.end()) {
+        *t = it->second;
+        return true;
+    }
+    const auto bt = g_bucket_table.find(bucket_of(k));
+    if (bt == g_bucket_table.end())
         return false;
-    *t = it->second;
+    *t = bt->second;
     return true;
 }
 
@@ -247,6 +277,7 @@ void tune_store(const TuneKey &k, const LaunchTune &t)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tune_table[k] = t;
+    g_bucket_table[bucket_of(k)] = t;
 }
 
 TuneKey tune_key(int n, int w, int h, int levels, int64_t stride)
@@ -259,9 +290,17 @@ bool shape_valid(const mtb_launch_shape &s)
     if (s.pyramid_slots_pct < 25 || s.pyramid_slots_pct > 400 || s.bitmaps_blocks_pct < 25 ||
         s.bitmaps_blocks_pct > 100)
         return false;
+    if (s.pyramid_tile_group != 1 && s.pyramid_tile_group != 2 && s.pyramid_tile_group != 4)
+        return false;
+    if (s.bitmaps_waves != 2 && s.bitmaps_waves != 4 && s.bitmaps_waves != 8)
+        return false;
+    if (s.coarse_levels < -1 || s.coarse_levels > kCoarseLevels)
+        return false;
     for (int l = 0; l < kMaxLevels; ++l) {
-        const int r = s.search_rows[l];
+        const int r = s.search_rows[l], w = s.search_lanes[l];
         if (r != 0 && (r < kRowsStep || r > kRowsMax || r % kRowsStep != 0))
+            return false;
+        if (w != 0 && w != 8 && w != 16 && w != 32 && w != 64)
             return false;
     }
     return true;
@@ -271,9 +310,15 @@ LaunchTune from_shape(const mtb_launch_shape &s)
 {
     LaunchTune t;
     t.pyr_pct = s.pyramid_slots_pct;
+    t.pyr_group_log2 = s.pyramid_tile_group == 4 ? 2 : (s.pyramid_tile_group == 2 ? 1 : 0);
     t.bm_pct = s.bitmaps_blocks_pct;
-    for (int l = 0; l < kMaxLevels; ++l)
+    t.bm_waves = s.bitmaps_waves;
+    t.coarse = s.coarse_levels;
+    for (int l = 0; l < kMaxLevels; ++l) {
         t.rows[l] = s.search_rows[l];
+        const int w = s.search_lanes[l];
+        t.cw[l] = w == 8 ? 3 : w == 16 ? 4 : w == 32 ? 5 : w == 64 ? 6 : 0;
+    }
     return t;
 }
 
@@ -281,9 +326,130 @@ void to_shape(const LaunchTune &t, mtb_launch_shape *s)
 {
     memset(s, 0, sizeof(*s));
     s->pyramid_slots_pct = t.pyr_pct;
+    s->pyramid_tile_group = 1 << t.pyr_group_log2;
     s->bitmaps_blocks_pct = t.bm_pct;
-    for (int l = 0; l < kMaxLevels; ++l)
+    s->bitmaps_waves = t.bm_waves;
+    s->coarse_levels = t.coarse;
+    for (int l = 0; l < kMaxLevels; ++l) {
         s->search_rows[l] = t.rows[l];
+        s->search_lanes[l] = t.cw[l] ? 1 << t.cw[l] : 0;
+    }
+}
+
+// Device architecture and HIP runtime version that tuned shapes are valid for.
+std::string tune_platform()
+{
+    int dev = 0, ver = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        hipRuntimeGetVersion(&ver) != hipSuccess)
+        return std::string();
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos)
+        arch.resize(colon);
+    return arch + " hip-" + std::to_string(ver);
+}
+
+// Times candidate shapes for one key by the median of kReps calls of run(t)
+// (HIP events on s, after a warm-up call), changing one knob at a time from
+// the built-in shape and keeping a change only if it is at least 2 % faster.
+// run(t) enqueues a whole call that uses shape t for this key.
+template <typename Run>
+mtb_status tune_one(const Geometry &g, int npairs, int cus, hipStream_t s, Run run, LaunchTune *out_best,
+                    float *out_ms, float *out_default_ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        return MTB_ERR_DEVICE;
+    }
+    constexpr int kReps = 7;
+    auto time = [&](const LaunchTune &t, float *ms) -> mtb_status {
+        mtb_status r = run(t);
+        float v[kReps];
+        for (int k = 0; k < kReps && r == MTB_OK; ++k) {
+            if (hipEventRecord(e0, s) != hipSuccess)
+                return MTB_ERR_DEVICE;
+            r = run(t);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&v[k], e0, e1) != hipSuccess)
+                return MTB_ERR_DEVICE;
+        }
+        if (r != MTB_OK)
+            return r;
+        std::sort(v, v + kReps);
+        *ms = v[kReps / 2];
+        return MTB_OK;
+    };
+    LaunchTune best;
+    float best_ms = 0.f;
+    mtb_status st = time(best, &best_ms);
+    const float default_ms = best_ms;
+    auto consider = [&](const LaunchTune &cand) {
+        float ms = 0.f;
+        if (st == MTB_OK)
+            st = time(cand, &ms);
+        if (st == MTB_OK && ms < 0.98f * best_ms) {
+            best = cand;
+            best_ms = ms;
+        }
+    };
+    for (int pct : {50, 75, 150, 200}) {
+        LaunchTune c = best;
+        c.pyr_pct = pct;
+        consider(c);
+    }
+    for (int gl : {1, 2}) {
+        LaunchTune c = best;
+        c.pyr_group_log2 = gl;
+        consider(c);
+    }
+    for (int pct : {50, 75}) {
+        LaunchTune c = best;
+        c.bm_pct = pct;
+        consider(c);
+    }
+    for (int w : {2, 8}) {
+        LaunchTune c = best;
+        c.bm_waves = w;
+        consider(c);
+    }
+    if (npairs > 0) {
+        const int rule = coarse_level_count(g);
+        const int most = g.L < kCoarseLevels ? g.L : kCoarseLevels;
+        for (int cn : {rule - 1, rule + 1}) {
+            if (cn < 0 || cn > most)
+                continue;
+            LaunchTune c = best;
+            c.coarse = cn;
+            consider(c);
+        }
+        for (int l = g.L - 1 - coarse_levels_used(g, &best); l >= 0; --l) {
+            for (int cw : {3, 4, 5, 6}) {
+                LaunchTune c = best;
+                c.cw[l] = cw;
+                consider(c);
+            }
+            const int r0 = search_rows_rule(g, l, npairs, cus, best.cw[l]);
+            for (int r : {r0 / 2, 2 * r0}) {
+                if (r < kRowsStep || r > kRowsMax || r % kRowsStep != 0)
+                    continue;
+                LaunchTune c = best;
+                c.rows[l] = r;
+                consider(c);
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MTB_OK)
+        return st;
+    *out_best = best;
+    *out_ms = best_ms;
+    *out_default_ms = default_ms;
+    return MTB_OK;
 }
 
 // Items of a batch that share one launch set: same geometry and stride, at
@@ -389,6 +555,62 @@ constexpr int64_t kPairScratchWords =
     (((int64_t)kMaxLevels * kCounterWords + 2 * kMaxLevels + kSurfWords + kAlign / 4 - 1) / (kAlign / 4)) *
         (kAlign / 4) +
     kTicketWords;
+
+// A batch: one launch set per group of items that share geometry and stride,
+// each with its key's tuned shape (or, for the key ov_key, the shape ov_shape).
+mtb_status align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range, void *d_workspace,
+                       size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs, hipStream_t s,
+                       const TuneKey *ov_key, const LaunchTune *ov_shape)
+{
+    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH || !d_workspace || !d_shifts || !d_errs)
+        return MTB_ERR_INVALID_ARG;
+    if (exclude_range < 0 || exclude_range > 255)
+        return MTB_ERR_INVALID_ARG;
+    Geometry g;
+    for (int i = 0; i < n_items; ++i)
+        if (!batch_item_valid(h_items[i], &g))
+            return MTB_ERR_INVALID_ARG;
+    if (workspace_bytes < mtb_batch_workspace_bytes(h_items, n_items))
+        return MTB_ERR_WORKSPACE;
+    const int cus = current_device_cus();
+    if (cus <= 0)
+        return MTB_ERR_UNSUPPORTED;
+    uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
+    for (const BatchGroup &grp : batch_groups(h_items, n_items)) {
+        const mtb_batch_item &f = h_items[grp.first];
+        make_geometry(f.width, f.height, f.levels, &g);
+        PairSet ps;
+        int align = 16;
+        for (int k : grp.items) {
+            const mtb_batch_item &it = h_items[k];
+            ps.ref_img[ps.npairs] = ps.n;
+            ps.rgb[ps.n++] = it.d_ref_rgb;
+            ps.mov_img[ps.npairs] = ps.n;
+            ps.rgb[ps.n++] = it.d_mov_rgb;
+            ps.out_row[ps.npairs++] = k;
+            const int a1 = row_alignment(it.d_ref_rgb, it.row_stride), a2 = row_alignment(it.d_mov_rgb, it.row_stride);
+            align = a1 < align ? a1 : align;
+            align = a2 < align ? a2 : align;
+        }
+        SearchOutputs out;
+        memset(&out, 0, sizeof(out));
+        out.n_out = n_items;
+        out.shifts = d_shifts;
+        out.errs = d_errs;
+        ZeroArgs z;
+        memset(&z, 0, sizeof(z));
+        const TuneKey key = tune_key(ps.n, f.width, f.height, f.levels, f.row_stride);
+        LaunchTune t;
+        if (ov_key && *ov_key == key)
+            t = *ov_shape;
+        else
+            tune_lookup(key, &t);
+        const hipError_t e = enqueue_set(ps, g, f.row_stride, align, exclude_range, ws, out, z, cus, s, false, t);
+        if (e != hipSuccess)
+            return MTB_ERR_DEVICE;
+    }
+    return MTB_OK;
+}
 
 }  // namespace
 
@@ -762,73 +984,14 @@ mtb_status mtb_tune_stack(const uint8_t *const *h_d_rgb, int32_t n, int32_t widt
         return align_stack(h_d_rgb, n, width, height, row_stride, levels, exclude_range, ref_index, d_workspace,
                            workspace_bytes, d_shifts, d_errs, nullptr, false, s, false, &t);
     };
-    LaunchTune best;
-    mtb_status st = run(best);  // validates every argument before anything is timed
+    mtb_status st = run(LaunchTune());  // validates every argument before anything is timed
     if (st != MTB_OK)
         return st;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0)
-            (void)hipEventDestroy(e0);
-        return MTB_ERR_DEVICE;
-    }
-    constexpr int kReps = 7;
-    // Median event time of kReps calls with shape t, after one warm-up call.
-    auto time = [&](const LaunchTune &t, float *ms) -> mtb_status {
-        mtb_status r = run(t);
-        float v[kReps];
-        for (int k = 0; k < kReps && r == MTB_OK; ++k) {
-            if (hipEventRecord(e0, s) != hipSuccess)
-                return MTB_ERR_DEVICE;
-            r = run(t);
-            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&v[k], e0, e1) != hipSuccess)
-                return MTB_ERR_DEVICE;
-        }
-        if (r != MTB_OK)
-            return r;
-        std::sort(v, v + kReps);
-        *ms = v[kReps / 2];
-        return MTB_OK;
-    };
-    float best_ms = 0.f, default_ms = 0.f;
-    st = time(best, &best_ms);
-    default_ms = best_ms;
-    auto consider = [&](const LaunchTune &cand) {
-        float ms = 0.f;
-        if (st == MTB_OK)
-            st = time(cand, &ms);
-        if (st == MTB_OK && ms < 0.98f * best_ms) {
-            best = cand;
-            best_ms = ms;
-        }
-    };
-    for (int pct : {50, 75, 150, 200}) {
-        LaunchTune c = best;
-        c.pyr_pct = pct;
-        consider(c);
-    }
-    for (int pct : {50, 75}) {
-        LaunchTune c = best;
-        c.bm_pct = pct;
-        consider(c);
-    }
     Geometry g;
     make_geometry(width, height, levels, &g);  // valid: the first run checked it
-    const int cus = current_device_cus();
-    const int npairs = n - 1;
-    for (int l = levels - 1 - coarse_level_count(g); l >= 0 && npairs > 0; --l) {
-        const int r0 = search_rows_rule(g, l, npairs, cus);
-        for (int r : {r0 / 2, 2 * r0}) {
-            if (r < kRowsStep || r > kRowsMax || r % kRowsStep != 0)
-                continue;
-            LaunchTune c = best;
-            c.rows[l] = r;
-            consider(c);
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    LaunchTune best;
+    float best_ms = 0.f, default_ms = 0.f;
+    st = tune_one(g, n - 1, current_device_cus(), s, run, &best, &best_ms, &default_ms);
     if (st != MTB_OK)
         return st;
     // The winning shape leaves its results in d_shifts / d_errs as well.
@@ -882,6 +1045,84 @@ void mtb_tune_reset(void)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tune_table.clear();
+    g_bucket_table.clear();
+}
+
+mtb_status mtb_tune_save(const char *path)
+{
+    if (!path)
+        return MTB_ERR_INVALID_ARG;
+    const std::string platform = tune_platform();
+    if (platform.empty())
+        return MTB_ERR_UNSUPPORTED;
+    FILE *f = fopen(path, "w");
+    if (!f)
+        return MTB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    bool ok = fprintf(f, "mtb-tune 1 %s\n", platform.c_str()) > 0;
+    for (const auto &kv : g_tune_table) {
+        const TuneKey &k = kv.first;
+        const LaunchTune &t = kv.second;
+        ok = ok && fprintf(f, "%d %d %d %d %d  %d %d %d %d %d ", k.n, k.w, k.h, k.levels, k.align, t.pyr_pct,
+                           t.pyr_group_log2, t.bm_pct, t.bm_waves, t.coarse) > 0;
+        for (int l = 0; l < kMaxLevels && ok; ++l)
+            ok = fprintf(f, " %d", t.rows[l]) > 0;
+        for (int l = 0; l < kMaxLevels && ok; ++l)
+            ok = fprintf(f, " %d", t.cw[l]) > 0;
+        ok = ok && fprintf(f, "\n") > 0;
+    }
+    ok = (fclose(f) == 0) && ok;
+    return ok ? MTB_OK : MTB_ERR_INVALID_ARG;
+}
+
+mtb_status mtb_tune_load(const char *path, int32_t *h_loaded)
+{
+    if (!path || !h_loaded)
+        return MTB_ERR_INVALID_ARG;
+    *h_loaded = 0;
+    const std::string platform = tune_platform();
+    if (platform.empty())
+        return MTB_ERR_UNSUPPORTED;
+    FILE *f = fopen(path, "r");
+    if (!f)
+        return MTB_ERR_INVALID_ARG;
+    char line[1024];
+    std::vector<std::pair<TuneKey, LaunchTune>> got;
+    bool ok = fgets(line, sizeof(line), f) != nullptr;
+    // Shapes tuned on another architecture or HIP runtime are skipped whole.
+    const bool same = ok && std::string(line) == "mtb-tune 1 " + platform + "\n";
+    while (ok && same && fgets(line, sizeof(line), f)) {
+        TuneKey k;
+        LaunchTune t;
+        int used = 0;
+        const char *p = line;
+        ok = sscanf(p, "%d %d %d %d %d %d %d %d %d %d%n", &k.n, &k.w, &k.h, &k.levels, &k.align, &t.pyr_pct,
+                    &t.pyr_group_log2, &t.bm_pct, &t.bm_waves, &t.coarse, &used) == 10;
+        p += used;
+        for (int l = 0; l < 2 * kMaxLevels && ok; ++l) {
+            ok = sscanf(p, "%d%n", l < kMaxLevels ? &t.rows[l] : &t.cw[l - kMaxLevels], &used) == 1;
+            p += used;
+        }
+        if (!ok)
+            break;
+        mtb_launch_shape sh;
+        to_shape(t, &sh);
+        Geometry g;
+        ok = k.n >= 1 && k.n <= kMaxStack && (k.align == 1 || k.align == 4 || k.align == 16) &&
+             t.pyr_group_log2 >= 0 && t.pyr_group_log2 <= 2 && shape_valid(sh) &&
+             make_geometry(k.w, k.h, k.levels, &g);
+        for (int l = 0; l < kMaxLevels && ok; ++l)
+            ok = t.cw[l] == 0 || (t.cw[l] >= 3 && t.cw[l] <= 6);
+        if (ok)
+            got.push_back({k, t});
+    }
+    fclose(f);
+    if (!ok)
+        return MTB_ERR_INVALID_ARG;
+    for (const auto &kv : got)
+        tune_store(kv.first, kv.second);
+    *h_loaded = (int32_t)got.size();
+    return MTB_OK;
 }
 
 mtb_status mtb_apply_shifts(const uint8_t *const *h_d_rgb, int32_t n, int32_t width, int32_t height,
@@ -952,49 +1193,47 @@ mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32
                            void *d_workspace, size_t workspace_bytes, int32_t *d_shifts,
                            uint32_t *d_errs, void *stream)
 {
-    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH || !d_workspace || !d_shifts || !d_errs)
+    return align_batch(h_items, n_items, exclude_range, d_workspace, workspace_bytes, d_shifts, d_errs,
+                       (hipStream_t)stream, nullptr, nullptr);
+}
+
+mtb_status mtb_tune_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range,
+                          void *d_workspace, size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                          void *stream, int32_t *h_tuned)
+{
+    if (!h_tuned)
         return MTB_ERR_INVALID_ARG;
-    if (exclude_range < 0 || exclude_range > 255)
-        return MTB_ERR_INVALID_ARG;
-    Geometry g;
-    for (int i = 0; i < n_items; ++i)
-        if (!batch_item_valid(h_items[i], &g))
-            return MTB_ERR_INVALID_ARG;
-    if (workspace_bytes < mtb_batch_workspace_bytes(h_items, n_items))
-        return MTB_ERR_WORKSPACE;
-    const int cus = current_device_cus();
-    if (cus <= 0)
-        return MTB_ERR_UNSUPPORTED;
-    hipStream_t s = (hipStream_t)stream;
-    uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
+    *h_tuned = 0;
+    const hipStream_t s = (hipStream_t)stream;
+    mtb_status st = align_batch(h_items, n_items, exclude_range, d_workspace, workspace_bytes, d_shifts, d_errs, s,
+                                nullptr, nullptr);  // validates every argument first
+    if (st != MTB_OK)
+        return st;
+    // One group key after another: the whole batch is timed with candidate
+    // shapes for that key, the other keys at their current shapes.
+    std::vector<TuneKey> done;
     for (const BatchGroup &grp : batch_groups(h_items, n_items)) {
         const mtb_batch_item &f = h_items[grp.first];
+        const TuneKey key = tune_key(2 * (int)grp.items.size(), f.width, f.height, f.levels, f.row_stride);
+        if (std::find(done.begin(), done.end(), key) != done.end())
+            continue;
+        done.push_back(key);
+        Geometry g;
         make_geometry(f.width, f.height, f.levels, &g);
-        PairSet ps;
-        int align = 16;
-        for (int k : grp.items) {
-            const mtb_batch_item &it = h_items[k];
-            ps.ref_img[ps.npairs] = ps.n;
-            ps.rgb[ps.n++] = it.d_ref_rgb;
-            ps.mov_img[ps.npairs] = ps.n;
-            ps.rgb[ps.n++] = it.d_mov_rgb;
-            ps.out_row[ps.npairs++] = k;
-            const int a1 = row_alignment(it.d_ref_rgb, it.row_stride), a2 = row_alignment(it.d_mov_rgb, it.row_stride);
-            align = a1 < align ? a1 : align;
-            align = a2 < align ? a2 : align;
-        }
-        SearchOutputs out;
-        memset(&out, 0, sizeof(out));
-        out.n_out = n_items;
-        out.shifts = d_shifts;
-        out.errs = d_errs;
-        ZeroArgs z;
-        memset(&z, 0, sizeof(z));
-        const hipError_t e = enqueue_set(ps, g, f.row_stride, align, exclude_range, ws, out, z, cus, s);
-        if (e != hipSuccess)
-            return MTB_ERR_DEVICE;
+        auto run = [&](const LaunchTune &t) {
+            return align_batch(h_items, n_items, exclude_range, d_workspace, workspace_bytes, d_shifts, d_errs, s,
+                               &key, &t);
+        };
+        LaunchTune best;
+        float ms = 0.f, def = 0.f;
+        st = tune_one(g, (int)grp.items.size(), current_device_cus(), s, run, &best, &ms, &def);
+        if (st != MTB_OK)
+            return st;
+        tune_store(key, best);
+        ++*h_tuned;
     }
-    return MTB_OK;
+    return align_batch(h_items, n_items, exclude_range, d_workspace, workspace_bytes, d_shifts, d_errs, s, nullptr,
+                       nullptr);
 }
 
 size_t mtb_quadrant_workspace_bytes(int32_t width, int32_t height, int64_t row_stride, int32_t levels)

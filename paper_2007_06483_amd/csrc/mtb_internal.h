@@ -78,6 +78,8 @@ struct PyramidArgs {
     int32_t xcd_tiles;       // tiles of each XCD's contiguous share of the work
     int32_t align;           // 16, 4 or 1: alignment every RGB row start is known to have
     int32_t merge;           // 1: histograms merged through per-XCD copies (see k_pyramid)
+    int32_t group_log2;      // a workgroup takes 2^group_log2 consecutive tiles of a row at a time
+    int32_t pad_;
     Geometry g;
 };
 
@@ -142,6 +144,8 @@ struct SearchArgs {
     int32_t level;                   // fine kernel: the level searched
     int32_t coarse_n;                // levels L-1 .. L-coarse_n searched exhaustively
     int32_t rows_per_stream;         // rows per lane in one work unit
+    int32_t cw_log2;                 // fine kernel: lanes per row stream (log2, 3..6), 0: the rule
+    int32_t pad_;
     SearchOutputs out;
     Geometry g;
 };
@@ -196,21 +200,30 @@ hipError_t launch_kernel(const char *name, void (*k)(A), dim3 grid, dim3 block, 
 }
 
 // Launch shapes a tuner may change (results never depend on them): k_pyramid
-// and k_bitmaps workgroups as a percentage of one round of resident
-// workgroups, and k_search_fine rows per stream per level (0: the rule that
-// keeps the grid within one resident round).
+// workgroups as a percentage of one resident round and the tiles of a row a
+// workgroup takes at a time (2^pyr_group_log2); k_bitmaps workgroups as a
+// percentage of one resident round and wavefronts per workgroup; how many of
+// the coarsest levels are searched over exhaustive windows (-1: the rule);
+// and per fine level the rows per stream (0: the rule that keeps the grid
+// within one resident round) and the lanes per row stream (log2, 3 .. 6; 0:
+// the rule that pads rows least).
 constexpr int kRowsStep = 4;   // rows per stream come in multiples of this
 constexpr int kRowsMax = 64;
 struct LaunchTune {
     int32_t pyr_pct = 100;
+    int32_t pyr_group_log2 = 0;
     int32_t bm_pct = 100;
+    int32_t bm_waves = 4;
+    int32_t coarse = -1;
     int32_t rows[kMaxLevels] = {};
+    int32_t cw[kMaxLevels] = {};
 };
 
 // Launch helpers (mtb_kernels.hip).  Each returns the hipError_t of its launches.
 hipError_t launch_zero(const ZeroArgs &a, hipStream_t s);
-hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s, int slots_pct = 100);
-hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s, int blocks_pct = 100);
+hipError_t launch_pyramid(const PyramidArgs &a, int device_cus, hipStream_t s, int slots_pct = 100,
+                          int group_log2 = 0);
+hipError_t launch_bitmaps(const BitmapArgs &a, int device_cus, hipStream_t s, int blocks_pct = 100, int waves = 4);
 hipError_t launch_apply(const ApplyArgs &a, int device_cus, hipStream_t s);
 // The byte-map comparison path: T/E as 255/0 bytes, and the search over them.
 hipError_t launch_bytemaps(const BitmapArgs &a, int device_cus, hipStream_t s);
@@ -225,10 +238,13 @@ hipError_t launch_quadrant_flag(const int32_t *d_shifts, int32_t tol, int32_t *d
 // Levels L-1 .. L-coarse_level_count(g) are searched exhaustively; the others
 // are the fine levels.
 int coarse_level_count(const Geometry &g);
-// Rows per stream launch_search uses at fine level l without a tuned value.
-int search_rows_rule(const Geometry &g, int l, int npairs, int device_cus);
-int search_row_blocks(const Geometry &g, int l, int rows);
-// rows: per-level rows per stream (LaunchTune::rows), or null for the rule.
-hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s, const int32_t *rows = nullptr);
+// Rows per stream launch_search uses at fine level l without a tuned value
+// (for a stream width cw_log2, 0: the rule).
+int search_rows_rule(const Geometry &g, int l, int npairs, int device_cus, int cw_log2 = 0);
+int search_row_blocks(const Geometry &g, int l, int rows, int cw_log2 = 0);
+// Coarse levels a search runs with shape t (null: the rule).
+int coarse_levels_used(const Geometry &g, const LaunchTune *t);
+// t: the launch shape (rows and lanes per stream per level, coarse levels), or null for the rules.
+hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s, const LaunchTune *t = nullptr);
 
 }  // namespace mtb

@@ -156,8 +156,18 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     // cache line two of them share is fetched from HBM once.
     const int slot = blockIdx.x / kXcds, slots = gridDim.x / kXcds;
     const int64_t xb = (int64_t)(blockIdx.x % kXcds) * a.xcd_tiles;
-    const int64_t t0 = xb + slot;
+    const int64_t t0 = xb + ((int64_t)slot << a.group_log2);
     const int64_t t1 = xb + a.xcd_tiles < total ? xb + a.xcd_tiles : total;
+    // The share is walked in groups of 2^group_log2 consecutive tiles (one
+    // launch-shape knob): slot s takes groups s, s + slots, ..., each group's
+    // tiles one after another.
+    const int64_t gmask = ((int64_t)1 << a.group_log2) - 1;
+    auto next_tile = [&](int64_t t) -> int64_t {
+        const int64_t r = t - xb;
+        if ((r & gmask) != gmask)
+            return t + 1;
+        return xb + (((r >> a.group_log2) + slots) << a.group_log2);
+    };
 
     // Levels 5 and 6 of the `count` tiles parked in ring `bank` (image img).
     // Call after a barrier that follows the tiles' level-4 writes; thread
@@ -296,7 +306,7 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
     }
 
     int cur = -1, cur_tiles = 0;
-    for (int64_t t = t0; t < t1; t += slots) {
+    for (int64_t t = t0; t < t1; t = next_tile(t)) {
         int img, X0, Y0;
         locate(t, img, X0, Y0);
         if (img != cur) {
@@ -375,9 +385,9 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
             }
         }
         // ---- prefetch the next tile's RGB while this one is processed
-        if (fast16 && t + slots < t1) {
+        if (fast16 && next_tile(t) < t1) {
             int img2, X2, Y2;
-            locate(t + slots, img2, X2, Y2);
+            locate(next_tile(t), img2, X2, Y2);
             const int x2 = X2 + 16 * bx;
             if (x2 + 15 < g.W)
                 load_rgb16(a.rgb[img2], a.stride, x2, Y2 + 16 * wave + 4 * by, g.H, q);
@@ -702,15 +712,16 @@ __device__ __forceinline__ void te_bits(const uint32_t (&t)[8], const Thresholds
 // byte transpose that lets the per-byte answers be gathered into bit order
 // with one shift and one and-or per dword.  Lane i then stores dword i of the
 // chunk's T words and of its E words.
-__global__ __launch_bounds__(256) void k_bitmaps(BitmapArgs a)
+template <int kW>
+__global__ __launch_bounds__(64 * kW) void k_bitmaps(BitmapArgs a)
 {
     const int wave = wave_id();
     const int lane = threadIdx.x & 63;
     const Geometry &g = a.g;
     const int64_t per_image = a.chunk_start[g.L];
     const int64_t total = per_image * a.n;
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t nwaves = (int64_t)gridDim.x * kW;
+    const int64_t gw = (int64_t)blockIdx.x * kW + wave;
     const int64_t per_wave = (total + nwaves - 1) / nwaves;
     const int64_t c0 = gw * per_wave;
     const int64_t c1 = c0 + per_wave < total ? c0 + per_wave : total;
@@ -884,10 +895,11 @@ __device__ __forceinline__ void shift3c(const uint32_t *m, uint32_t r, uint32_t 
 struct UnitPlan {
     int cw_log2, units_x, units;
 };
-__host__ __device__ __forceinline__ UnitPlan plan_level(const LevelGeom &lv, int rows)
+__host__ __device__ __forceinline__ UnitPlan plan_level(const LevelGeom &lv, int rows, int cw_force)
 {
     const int cols = lv.wpr;  // two-word columns per row (n32 / 2)
-    // The stream width (8 .. 64 lanes) that pads the row least; ties go wide.
+    // The stream width (8 .. 64 lanes) that pads the row least, ties going
+    // wide; cw_force (3 .. 6, a launch-shape knob) overrides it.
     int best = 6, best_pad = 1 << 30;
     for (int c = 6; c >= 3; --c) {
         const int pad = (((cols + (1 << c) - 1) >> c) << c) - cols;
@@ -896,6 +908,8 @@ __host__ __device__ __forceinline__ UnitPlan plan_level(const LevelGeom &lv, int
             best_pad = pad;
         }
     }
+    if (cw_force >= 3 && cw_force <= 6)
+        best = cw_force;
     UnitPlan p;
     p.cw_log2 = best;
     p.units_x = (cols + (1 << best) - 1) >> best;
@@ -1486,7 +1500,7 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
     const int pair = blockIdx.y;
     level_base(a, pair, sbase);
     const LevelGeom &lv = a.g.lv[a.level];
-    const UnitPlan p = plan_level(lv, a.rows_per_stream);
+    const UnitPlan p = plan_level(lv, a.rows_per_stream, a.cw_log2);
     uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int unit = blockIdx.x * 4 + wave_id();
     if (unit < p.units)
@@ -1719,14 +1733,14 @@ __global__ void k_quadrant_flag(QuadFlagArgs a)
 // (registers and LDS), from the runtime's occupancy calculator; cached once
 // per kernel (each instantiation has its own cache, so kernels that share an
 // argument type do not share a value).
-template <auto K>
+template <auto K, int kThreads = 256>
 int resident_per_cu()
 {
     static std::atomic<int> cached{0};
     int v = cached.load(std::memory_order_relaxed);
     if (v == 0) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, K, 256, 0) != hipSuccess || n < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, K, kThreads, 0) != hipSuccess || n < 1)
             n = 1;
         cached.store(n, std::memory_order_relaxed);
         v = n;
@@ -1746,17 +1760,19 @@ hipError_t launch_zero(const ZeroArgs &a, hipStream_t s)
     return launch_kernel("k_zero", k_zero, dim3(blocks, a.count), dim3(256), s, a);
 }
 
-hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s, int slots_pct)
+hipError_t launch_pyramid(const PyramidArgs &in, int cus, hipStream_t s, int slots_pct, int group_log2)
 {
     PyramidArgs a = in;
     a.tiles_x = (a.g.W + kTileW - 1) / kTileW;
     a.tiles_y = (a.g.H + kTileH - 1) / kTileH;
+    a.group_log2 = group_log2;
     const int64_t total = (int64_t)a.tiles_x * a.tiles_y * a.n;
     // One round of resident workgroups (scaled by slots_pct); each XCD gets
-    // the same number of slots (see k_pyramid).
+    // the same number of slots (see k_pyramid), at most one per tile group.
     const int64_t share = (total + kXcds - 1) / kXcds;
+    const int64_t groups = (share + (1 << group_log2) - 1) >> group_log2;
     int64_t slots = (int64_t)cus * resident_per_cu<k_pyramid>() * slots_pct / (100 * kXcds);
-    slots = slots > share ? share : (slots < 1 ? 1 : slots);
+    slots = slots > groups ? groups : (slots < 1 ? 1 : slots);
     a.xcd_tiles = (int32_t)share;
     const int blocks = (int)(slots * kXcds);
     a.merge = blocks >= kMergeMinWgsPerImage * a.n;
@@ -1826,13 +1842,25 @@ hipError_t launch_search_bytes(SearchArgs a, int cus, hipStream_t s)
     return hipSuccess;
 }
 
-hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s, int blocks_pct)
+template <int kW>
+hipError_t launch_bitmaps_w(const BitmapArgs &a, int cus, hipStream_t s, int blocks_pct)
 {
     const int64_t total = a.chunk_start[a.g.L] * a.n;
-    int64_t blocks = (total + 3) / 4;
-    const int64_t cap = (int64_t)cus * resident_per_cu<k_bitmaps>() * blocks_pct / 100;
+    int64_t blocks = (total + kW - 1) / kW;
+    const int64_t cap = (int64_t)cus * resident_per_cu<k_bitmaps<kW>, 64 * kW>() * blocks_pct / 100;
     blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
-    return launch_kernel("k_bitmaps", k_bitmaps, dim3((unsigned)blocks), dim3(256), s, a);
+    return launch_kernel("k_bitmaps", k_bitmaps<kW>, dim3((unsigned)blocks), dim3(64 * kW), s, a);
+}
+
+hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s, int blocks_pct, int waves)
+{
+    // Wavefronts walk their chunks independently; the workgroup size only
+    // changes how the launch is cut (a launch-shape knob).
+    if (waves == 2)
+        return launch_bitmaps_w<2>(a, cus, s, blocks_pct);
+    if (waves == 8)
+        return launch_bitmaps_w<8>(a, cus, s, blocks_pct);
+    return launch_bitmaps_w<4>(a, cus, s, blocks_pct);
 }
 
 // The i-th coarsest level is searched exhaustively when i < kCoarseLevels and
@@ -1851,12 +1879,12 @@ int coarse_level_count(const Geometry &g)
 // in turn, so with a row of blocks whose length is a multiple of kXcds every
 // pair's workgroup for one unit runs on the same XCD, whose L2 then serves
 // the shared reference rows.
-int search_row_blocks(const Geometry &g, int l, int rows)
+int search_row_blocks(const Geometry &g, int l, int rows, int cw_log2)
 {
-    return ((plan_level(g.lv[l], rows).units + 3) / 4 + kXcds - 1) / kXcds * kXcds;
+    return ((plan_level(g.lv[l], rows, cw_log2).units + 3) / 4 + kXcds - 1) / kXcds * kXcds;
 }
 
-int search_rows_rule(const Geometry &g, int l, int npairs, int cus)
+int search_rows_rule(const Geometry &g, int l, int npairs, int cus, int cw_log2)
 {
     // Rows per stream: the fewest (a multiple of the batches in flight) that
     // keep the grid within one round of resident workgroups, so that every
@@ -1865,15 +1893,23 @@ int search_rows_rule(const Geometry &g, int l, int npairs, int cus)
     static_assert(kRowsStep == kSearchBatch * kSearchDepth, "rows per stream fill whole batches");
     const int64_t resident = (int64_t)cus * resident_per_cu<k_search_fine>();
     int rows = kRowsStep;
-    while (rows < kRowsMax && (int64_t)search_row_blocks(g, l, rows) * npairs > resident)
+    while (rows < kRowsMax && (int64_t)search_row_blocks(g, l, rows, cw_log2) * npairs > resident)
         rows += kRowsStep;
     return rows;
 }
 
-hipError_t launch_search(SearchArgs a, int cus, hipStream_t s, const int32_t *tuned_rows)
+int coarse_levels_used(const Geometry &g, const LaunchTune *t)
+{
+    if (!t || t->coarse < 0)
+        return coarse_level_count(g);
+    const int most = g.L < kCoarseLevels ? g.L : kCoarseLevels;
+    return t->coarse < most ? t->coarse : most;
+}
+
+hipError_t launch_search(SearchArgs a, int cus, hipStream_t s, const LaunchTune *t)
 {
     const Geometry &g = a.g;
-    const int cn = coarse_level_count(g);
+    const int cn = coarse_levels_used(g, t);
     a.coarse_n = cn;
     hipError_t e = hipSuccess;
     if (cn > 0) {
@@ -1885,11 +1921,13 @@ hipError_t launch_search(SearchArgs a, int cus, hipStream_t s, const int32_t *tu
             return e;
     }
     for (int l = g.L - 1 - cn; l >= 0; --l) {
-        const int rows = tuned_rows && tuned_rows[l] > 0 ? tuned_rows[l] : search_rows_rule(g, l, a.npairs, cus);
+        const int cw = t ? t->cw[l] : 0;
+        const int rows = t && t->rows[l] > 0 ? t->rows[l] : search_rows_rule(g, l, a.npairs, cus, cw);
         a.level = l;
         a.rows_per_stream = rows;
-        e = launch_kernel("k_search_fine", k_search_fine, dim3(search_row_blocks(g, l, rows), a.npairs), dim3(256),
-                          s, a);
+        a.cw_log2 = cw;
+        e = launch_kernel("k_search_fine", k_search_fine, dim3(search_row_blocks(g, l, rows, cw), a.npairs),
+                          dim3(256), s, a);
         if (e != hipSuccess)
             return e;
     }

@@ -233,23 +233,70 @@ def widen_for_dma(im):
     return view, x - xa
 
 
-def footprint_bytes(mtb, n: int, width: int, height: int, levels: int, host_staged: bool = False) -> int:
-    """Device bytes a stack request holds while in flight: its workspace, and for
-    a host-staged request the device copies of its n images in front of it."""
-    ws = int(mtb.mtb_stack_workspace_bytes(n, width, height, levels))
+def plain_workspace_bytes(mtb, n: int, width: int, height: int, levels: int) -> int:
+    """Workspace of a stack run as plain per-image and per-pair calls: n pyramid
+    buffers, n bitmaps buffers and n - 1 pair-search workspaces."""
+    pyr = int(mtb.mtb_pyramid_bytes(width, height, levels))
+    bms = int(mtb.mtb_bitmaps_bytes(width, height, levels))
+    pws = int(mtb.mtb_pair_workspace_bytes(levels))
+    if min(pyr, bms, pws) <= 0 or n < 1:
+        raise ValueError("invalid stack request")
+    return n * (pyr + bms) + (n - 1) * pws
+
+
+def footprint_bytes(mtb, n: int, width: int, height: int, levels: int, host_staged: bool = False,
+                    plain: bool = False) -> int:
+    """Device bytes a stack request holds while in flight: its workspace (that of
+    mtb_align_stack, or with plain that of the per-image and per-pair calls), and
+    for a host-staged request the device copies of its n images in front of it."""
+    ws = (plain_workspace_bytes(mtb, n, width, height, levels) if plain
+          else int(mtb.mtb_stack_workspace_bytes(n, width, height, levels)))
     if ws <= 0:
         raise ValueError("invalid stack request")
     return ws + (n * staged_image_bytes(width, height) if host_staged else 0)
 
 
-def gpu_executor(pool_buffer, slots: int):
+def _plain_stack(mtb, images, req, ws, shifts, errs, stream):
+    """One stack as plain calls: every image's pyramid and bitmaps, then every
+    moving image against the reference (the reference's row stays (0, 0), 0)."""
+    n = len(images)
+    h, w = int(images[0].shape[0]), int(images[0].shape[1])
+    L = req.levels
+    ref = req.ref_index if req.ref_index >= 0 else n // 2
+    pyr = int(mtb.mtb_pyramid_bytes(w, h, L))
+    bms = int(mtb.mtb_bitmaps_bytes(w, h, L))
+    pws = int(mtb.mtb_pair_workspace_bytes(L))
+    shifts.zero_()
+    errs.zero_()
+    bitmaps = []
+    for i, im in enumerate(images):
+        p = ws[i * pyr:(i + 1) * pyr]
+        b = ws[n * pyr + i * bms:n * pyr + (i + 1) * bms]
+        mtb.mtb_build_pyramid(im, L, pyramid=p, stream=stream)
+        mtb.mtb_bitmaps(p, w, h, L, exclude_range=req.exclude_range, bitmaps=b, stream=stream)
+        bitmaps.append(b)
+    base = n * (pyr + bms)
+    k = 0
+    for i in range(n):
+        if i == ref:
+            continue
+        mtb.mtb_align_pair(bitmaps[ref], bitmaps[i], w, h, L, workspace=ws[base + k * pws:base + (k + 1) * pws],
+                           shift=shifts[i], err=errs[i:i + 1], stream=stream)
+        k += 1
+
+
+def gpu_executor(pool_buffer, slots: int, plain: bool = False):
     """Executor and poll functions that run requests through libmtb on `slots` streams.
 
     pool_buffer is a uint8 device tensor holding the serving pool; request
     footprints are views into it.  A request whose images are CPU tensors is
     host-staged: its footprint starts with one device image per input (see
     footprint_bytes), filled by mtb_stage_rgb on the slot's stream, and the
-    workspace follows.  Streams are created at default priority.
+    workspace follows.  Streams are created at default priority.  With plain
+    (the per-call path, for comparison) a stack runs as mtb_build_pyramid and
+    mtb_bitmaps per image and mtb_align_pair per moving image, each its own
+    launch sequence, instead of one mtb_align_stack call; the results are the
+    same.
     """
     import torch
 
@@ -280,9 +327,12 @@ def gpu_executor(pool_buffer, slots: int):
         with torch.cuda.stream(s):
             shifts = torch.empty((n, 2), dtype=torch.int32, device=pool_buffer.device)
             errs = torch.empty(n, dtype=torch.int32, device=pool_buffer.device)
-            mtb.mtb_align_stack(images, req.levels, exclude_range=req.exclude_range,
-                                ref_index=req.ref_index, workspace=ws, shifts=shifts, errs=errs,
-                                stream=s)
+            if plain:
+                _plain_stack(mtb, images, req, ws, shifts, errs, s)
+            else:
+                mtb.mtb_align_stack(images, req.levels, exclude_range=req.exclude_range,
+                                    ref_index=req.ref_index, workspace=ws, shifts=shifts, errs=errs,
+                                    stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
         return (ev, shifts, errs)

@@ -175,3 +175,41 @@ def test_host_staged_serving_equals_device_staged(mtb):
     host = [np.ascontiguousarray(synth.serve_crop(base, r, i)) for i in range(r["n"])]
     want = oracle.align_stack(host, r["levels"], ref_index=r["n"] // 2, threads=4)
     assert np.array_equal(out[True][r["rid"]].shifts.cpu().numpy(), want["shifts"])
+
+
+@pytest.mark.timeout(600)
+def test_plain_per_call_serving_equals_stack_serving(mtb):
+    """The per-call comparison path of the served bench (per-image pyramid and
+    bitmaps calls, one pair call per moving image) serves the same requests
+    with the same results as one mtb_align_stack call per request."""
+    from paper_2007_06483_amd.serving import Request, Server, footprint_bytes, gpu_executor
+
+    BW, BH = 1400, 900
+    base = synth.make_serve_base(BW, BH, 12, n_blobs=60)
+    base_dev = [torch.from_numpy(b).to(DEV) for b in base]
+    specs = synth.serve_requests(13, 300.0, 0.1, BW, BH, mp_range=(0.05, 0.6))
+    assert len(specs) >= 10
+    out = {}
+    for plain in (False, True):
+        reqs = [Request(rid=r["rid"], arrival=0.0 if k < 6 else r["arrival"],
+                        images=[synth.serve_crop(base_dev, r, i) for i in range(r["n"])], levels=r["levels"],
+                        workspace_bytes=footprint_bytes(mtb, r["n"], r["width"], r["height"], r["levels"],
+                                                        plain=plain))
+                for k, r in enumerate(specs)]
+        slots = 4
+        pool_bytes = slots * max(q.workspace_bytes for q in reqs) + 4096
+        pool = torch.empty(pool_bytes, dtype=torch.uint8, device=DEV)
+        execute, poll = gpu_executor(pool, slots, plain=plain)
+        srv = Server(pool_bytes, slots, execute, poll)
+        out[plain] = srv.run(reqs)
+        torch.cuda.synchronize()
+        assert srv.max_in_flight > 1
+    for a, b in zip(out[False], out[True]):
+        assert a.rid == b.rid
+        assert torch.equal(a.shifts, b.shifts), a.rid
+        assert torch.equal(a.errs, b.errs), a.rid
+    r = specs[len(specs) // 3]
+    host = [np.ascontiguousarray(synth.serve_crop(base, r, i)) for i in range(r["n"])]
+    want = oracle.align_stack(host, r["levels"], ref_index=r["n"] // 2, threads=4)
+    assert np.array_equal(out[True][r["rid"]].shifts.cpu().numpy(), want["shifts"])
+    assert np.array_equal(out[True][r["rid"]].errs.cpu().numpy().astype(np.int64), want["errs"])

@@ -118,6 +118,11 @@ def test_host_staged_footprint_holds_the_images_before_the_workspace():
     assert footprint_bytes(mtb, n, w, h, L, host_staged=True) == ws + n * staged_image_bytes(w, h)
     with pytest.raises(ValueError):
         footprint_bytes(mtb, 0, w, h, L)
+    # The per-call comparison path: n pyramids, n bitmaps, n - 1 pair workspaces.
+    plain = footprint_bytes(mtb, n, w, h, L, plain=True)
+    assert plain == n * (mtb.mtb_pyramid_bytes(w, h, L) + mtb.mtb_bitmaps_bytes(w, h, L)) + \
+        (n - 1) * mtb.mtb_pair_workspace_bytes(L)
+    assert footprint_bytes(mtb, n, w, h, L, host_staged=True, plain=True) == plain + n * staged_image_bytes(w, h)
 
 
 def test_widen_for_dma_aligns_every_offset_and_keeps_the_crop():

@@ -18,10 +18,14 @@ def clean_table():
 def test_set_lookup_and_reset():
     key = (7, 6000, 4000, 18000, 7)
     assert mtb.mtb_tuned_shape(*key) is None
-    mtb.mtb_set_shape(*key, {"pyramid_slots_pct": 200, "bitmaps_blocks_pct": 75, "search_rows": [8, 0, 16]})
+    mtb.mtb_set_shape(*key, {"pyramid_slots_pct": 200, "pyramid_tile_group": 2, "bitmaps_blocks_pct": 75,
+                             "bitmaps_waves": 8, "coarse_levels": 2, "search_rows": [8, 0, 16],
+                             "search_lanes": [0, 16, 64]})
     got = mtb.mtb_tuned_shape(*key)
     assert got["pyramid_slots_pct"] == 200 and got["bitmaps_blocks_pct"] == 75
+    assert got["pyramid_tile_group"] == 2 and got["bitmaps_waves"] == 8 and got["coarse_levels"] == 2
     assert got["search_rows"][:4] == [8, 0, 16, 0]
+    assert got["search_lanes"][:4] == [0, 16, 64, 0]
     # The key distinguishes image count, size, levels and the row-stride class.
     assert mtb.mtb_tuned_shape(6, 6000, 4000, 18000, 7) is None
     assert mtb.mtb_tuned_shape(7, 6000, 4000, 18000, 6) is None
@@ -34,7 +38,9 @@ def test_set_lookup_and_reset():
 @pytest.mark.parametrize("bad", [
     {"pyramid_slots_pct": 24}, {"pyramid_slots_pct": 401}, {"bitmaps_blocks_pct": 24},
     {"bitmaps_blocks_pct": 101}, {"search_rows": [2]}, {"search_rows": [6]}, {"search_rows": [68]},
-    {"search_rows": [0, -4]},
+    {"search_rows": [0, -4]}, {"pyramid_tile_group": 3}, {"pyramid_tile_group": 0}, {"bitmaps_waves": 1},
+    {"bitmaps_waves": 16}, {"coarse_levels": -2}, {"coarse_levels": 4}, {"search_lanes": [4]},
+    {"search_lanes": [0, 128]}, {"search_lanes": [24]},
 ])
 def test_out_of_range_shapes_are_refused(bad):
     shape = {"pyramid_slots_pct": 100, "bitmaps_blocks_pct": 100, "search_rows": []}
@@ -42,6 +48,30 @@ def test_out_of_range_shapes_are_refused(bad):
     with pytest.raises(RuntimeError):
         mtb.mtb_set_shape(7, 640, 480, 1920, 5, shape)
     assert mtb.mtb_tuned_shape(7, 640, 480, 1920, 5) is None
+
+
+def test_a_shape_serves_its_size_bucket():
+    # 6000x4000 and 6100x3950 share the half-octave bucket round(2 log2(w h)) = 49
+    # (same images, levels and stride class); 3000x2000 (bucket 45) does not.
+    mtb.mtb_set_shape(7, 6000, 4000, 18000, 7, {"pyramid_slots_pct": 150, "search_rows": [12]})
+    near = mtb.mtb_tuned_shape(7, 6100, 3950, 18304, 7)
+    assert near is not None and near["pyramid_slots_pct"] == 150 and near["search_rows"][0] == 12
+    assert mtb.mtb_tuned_shape(7, 3000, 2000, 9008, 7) is None
+    assert mtb.mtb_tuned_shape(6, 6100, 3950, 18304, 7) is None    # image count differs
+    assert mtb.mtb_tuned_shape(7, 6100, 3950, 18302, 7) is None    # stride class 1
+    # A size's own shape wins over its bucket's.
+    mtb.mtb_set_shape(7, 6100, 3950, 18304, 7, {"pyramid_slots_pct": 50})
+    assert mtb.mtb_tuned_shape(7, 6100, 3950, 18304, 7)["pyramid_slots_pct"] == 50
+
+
+def test_save_and_load_need_a_device():
+    # The file records the device architecture and HIP version, so without a
+    # device neither call can run; bad arguments are refused first.
+    L = mtb.lib()
+    n = ctypes.c_int32(-1)
+    assert L.mtb_tune_save(None) == 1
+    assert L.mtb_tune_load(None, ctypes.byref(n)) == 1
+    assert L.mtb_tune_load(b"/nonexistent", None) == 1
 
 
 def test_invalid_keys_are_refused():
