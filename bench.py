@@ -156,6 +156,45 @@ def measured_copy_GBps(torch, dev, nbytes=1 << 30, reps=5):
     return 2 * nbytes / best / 1e9
 
 
+# Read:write mixes of the streaming yardstick: read-only, a copy, the pyramid
+# pass's 3:1 and the bitmaps pass's 4:1.
+STREAM_MIXES = {"read_only": (1 << 30, 0), "copy_1to1": (1 << 29, 1 << 29), "pyramid_3to1": (768 << 20, 256 << 20),
+                "bitmaps_4to1": (820 << 20, 205 << 20)}
+
+
+def measured_stream_GBps(mtb, torch, dev, read_bytes, write_bytes, reps=7):
+    """Rate of the library's plain streaming kernel (mtb_probe_stream) for one
+    read:write mix: bytes read + written per second, median of `reps` launches,
+    each bracketed by events on the current stream."""
+    src = torch.empty(read_bytes, dtype=torch.uint8, device=dev)
+    src.fill_(3)
+    dst = torch.empty(max(write_bytes, 16), dtype=torch.uint8, device=dev)
+    mtb.mtb_probe_stream(src, read_bytes, dst, write_bytes)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mtb.mtb_probe_stream(src, read_bytes, dst, write_bytes)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    ts.sort()
+    return (read_bytes + write_bytes) / ts[len(ts) // 2] / 1e9
+
+
+def run_stream_probe(args, mtb, torch, dev):
+    """The streaming yardstick alone: every mix, GB/s against the 8 TB/s peak."""
+    out = {}
+    for name, (r, w) in STREAM_MIXES.items():
+        g = measured_stream_GBps(mtb, torch, dev, r, w)
+        out[name] = {"read_bytes": r, "write_bytes": w, "GBps": round(g, 1), "frac": round(g / PEAK_HBM_GBPS, 4)}
+        log(f"{name}: {g:.1f} GB/s")
+    out["torch_copy_1GiB"] = {"GBps": round(measured_copy_GBps(torch, dev), 1)}
+    print(json.dumps({"metric": "achievable HBM GB/s of a plain streaming kernel", "unit": "GB/s",
+                      "n_gpus": 1, "peak": PEAK_HBM_GBPS, "mixes": out}), flush=True)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -624,7 +663,7 @@ def main():
                     choices=["stack7_6000x4000", "stack7_6000x4000_chained", "stack7_6000x4000_bytemaps",
                              "pair_4096x3072", "pair_512x384",
                              "batch64_uneven",
-                             "served_poisson200", "apply7_6000x4000", "quadrants7_6000x4000"])
+                             "served_poisson200", "apply7_6000x4000", "quadrants7_6000x4000", "stream_probe"])
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mode: length of the run")
     ap.add_argument("--serve-slots", type=int, default=8, help="served mode: stacks in flight at most")
     ap.add_argument("--serve-plain-seconds", type=float, default=20.0,
@@ -678,6 +717,8 @@ def main():
         return run_apply(args, mtb, synth, torch, np, dev)
     if args.workload == "quadrants7_6000x4000":
         return run_quadrants(args, mtb, synth, torch, np, dev)
+    if args.workload == "stream_probe":
+        return run_stream_probe(args, mtb, torch, dev)
 
     log(f"generating {args.workload} ...")
     t0 = time.perf_counter()
@@ -768,6 +809,7 @@ def main():
     avg_s = total_ms / launches / 1e3
     achieved = algo[dominant] / avg_s / 1e9
     copy_gbps = measured_copy_GBps(torch, dev)
+    stream_gbps = measured_stream_GBps(mtb, torch, dev, *STREAM_MIXES["pyramid_3to1"])
     traffic = load_traffic(args.workload)
     step_gbps = algo["step"] / (ms_per_step / 1e3) / 1e9
     roofline = {
@@ -783,6 +825,9 @@ def main():
         "algorithmic_bytes_per_launch": algo[dominant],
         "copy_measured": round(copy_gbps, 1),
         "frac_of_copy": round(achieved / copy_gbps, 4),
+        # The library's own streaming kernel at the pass's 3:1 read:write mix.
+        "stream_3to1_measured": round(stream_gbps, 1),
+        "frac_of_stream_3to1": round(achieved / stream_gbps, 4),
         # The whole step against the same peak: model bytes of every kernel of
         # the step over the timed step time.
         "step_achieved": round(step_gbps, 1),

@@ -509,6 +509,22 @@ mtb_status mtb_profile_end(mtb_kernel_time *h_out, int32_t capacity, int32_t *h_
  */
 mtb_status mtb_profile_pause(int32_t paused);
 
+/*
+ * Measurement yardstick: one launch of a plain streaming kernel, so that a
+ * benchmark can time the rate this device reaches for the passes' own mixes
+ * of reads and writes (the pyramid pass reads 3 bytes per byte written, the
+ * bitmaps pass 4).  With write_bytes > 0 it reads R = read_bytes /
+ * write_bytes (integer part, 1 .. 4) contiguous 16-byte words of d_src per
+ * 16-byte word it writes to d_dst (one nontemporal store), write_bytes / 16
+ * times; with write_bytes = 0 it reads read_bytes of d_src in runs of four
+ * words and writes nothing.  Both pointers 16-byte aligned; d_dst may be
+ * NULL when write_bytes is 0.  The bytes written carry no meaning.
+ * Errors: MTB_ERR_INVALID_ARG (null or misaligned pointers, less than one
+ *         word, a ratio outside 1 .. 4), MTB_ERR_UNSUPPORTED (no device),
+ *         MTB_ERR_DEVICE.
+ */
+mtb_status mtb_probe_stream(const void *d_src, size_t read_bytes, void *d_dst, size_t write_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,7 @@ __all__ = [
     "mtb_profile_begin",
     "mtb_profile_end",
     "mtb_profile_pause",
+    "mtb_probe_stream",
 ]
 
 MTB_MAX_LEVELS = 16
@@ -235,6 +236,8 @@ def lib():
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
     L.mtb_batch_workspace_bytes.restype = sz
     L.mtb_align_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P]
+    L.mtb_probe_stream.argtypes = [P, sz, P, sz, P]
+    L.mtb_probe_stream.restype = ctypes.c_int
     L.mtb_tune_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P, ctypes.POINTER(i32)]
     L.mtb_tune_batch.restype = ctypes.c_int
     L.mtb_align_batch.restype = ctypes.c_int
@@ -651,6 +654,16 @@ def mtb_tune_batch(pairs, exclude_range: int = 4, workspace: torch.Tensor | None
            lib().mtb_tune_batch(items, n, exclude_range, _ptr(workspace), workspace.numel(), _ptr(shifts),
                                 _ptr(errs), _stream(stream), ctypes.byref(tuned)))
     return int(tuned.value)
+
+
+def mtb_probe_stream(src: torch.Tensor, read_bytes: int, dst: torch.Tensor | None, write_bytes: int,
+                     stream=None) -> None:
+    """One launch of the streaming yardstick kernel (reads read_bytes of src, writes write_bytes of dst)."""
+    _device_u8(src, "src")
+    if read_bytes > src.numel() or (write_bytes > 0 and (dst is None or write_bytes > dst.numel())):
+        raise ValueError("buffers smaller than the bytes to stream")
+    _check("mtb_probe_stream", lib().mtb_probe_stream(_ptr(src), read_bytes, _ptr(dst), write_bytes,
+                                                      _stream(stream)))
 
 
 def mtb_profile_begin(kernel_name: str | None = None) -> None:

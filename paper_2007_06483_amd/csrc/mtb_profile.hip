@@ -157,3 +157,95 @@ mtb_status mtb_profile_end(mtb_kernel_time *h_out, int32_t capacity, int32_t *h_
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- stream probe
+//
+// The rate a plain streaming kernel reaches on this device for a given mix of
+// reads and writes: the yardstick for the passes' achieved bandwidth (the
+// pyramid pass reads 3 bytes for every byte it writes, the bitmaps pass 4).
+
+namespace mtb {
+namespace {
+
+// Clang vector type, the operand type the nontemporal builtins accept.
+typedef uint32_t ProbeU32x4 __attribute__((ext_vector_type(4)));
+
+struct ProbeArgs {
+    const uint4 *src;
+    uint4 *dst;
+    int64_t units;  // work units: R consecutive 16-byte words read, one written (if any)
+    int32_t write;  // 0: read only
+    int32_t pad_;
+};
+
+// Unit q reads words q*R .. q*R+R-1 of src (R * 16 contiguous bytes per lane,
+// like the pyramid pass's 48-byte pixel runs for R = 3) and, when writing,
+// stores their xor to word q of dst with one 16-byte nontemporal store
+// (coalesced across the wavefront).  Each thread keeps four units' loads in
+// flight.  Read only, nothing is stored unless the data holds the
+// improbable value that keeps the loads alive.
+template <int R>
+__global__ __launch_bounds__(256) void k_stream_probe(ProbeArgs a)
+{
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    uint4 keep = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.units; q += 4 * T) {
+        uint4 v[4][R];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                v[u][k] = q + u * T < a.units ? a.src[(q + u * T) * R + k] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ProbeU32x4 x = {v[u][0].x, v[u][0].y, v[u][0].z, v[u][0].w};
+#pragma unroll
+            for (int k = 1; k < R; ++k) {
+                x.x ^= v[u][k].x;
+                x.y ^= v[u][k].y;
+                x.z ^= v[u][k].z;
+                x.w ^= v[u][k].w;
+            }
+            if (a.write && q + u * T < a.units)
+                __builtin_nontemporal_store(x, (ProbeU32x4 *)(a.dst + q + u * T));
+            keep.x ^= x.x;
+            keep.y ^= x.y;
+        }
+    }
+    if (!a.write && keep.x == 0x9e3779b9u && keep.y == 0x7f4a7c15u && a.dst)
+        a.dst[0] = keep;
+}
+
+}  // namespace
+}  // namespace mtb
+
+using namespace mtb;
+
+extern "C" mtb_status mtb_probe_stream(const void *d_src, size_t read_bytes, void *d_dst, size_t write_bytes,
+                                       void *stream)
+{
+    // Mixes of 1, 2, 3 or 4 bytes read per byte written, or read only.
+    const int64_t nread = (int64_t)(read_bytes / 16), nwrite = (int64_t)(write_bytes / 16);
+    if (!d_src || nread < 1 || (write_bytes > 0 && (!d_dst || nwrite < 1)) || (uintptr_t)d_src % 16 != 0 ||
+        (uintptr_t)d_dst % 16 != 0)
+        return MTB_ERR_INVALID_ARG;
+    const int64_t ratio = nwrite > 0 ? nread / nwrite : 4;
+    if (ratio < 1 || ratio > 4)
+        return MTB_ERR_INVALID_ARG;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return MTB_ERR_UNSUPPORTED;
+    const ProbeArgs a{(const uint4 *)d_src, (uint4 *)d_dst, nwrite > 0 ? nwrite : nread / 4, nwrite > 0 ? 1 : 0, 0};
+    // Four resident workgroups of 256 threads per compute unit.
+    const dim3 grid((unsigned)(cus * 4)), block(256);
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    switch (ratio) {
+    case 1: e = launch_kernel("k_stream_probe", k_stream_probe<1>, grid, block, s, a); break;
+    case 2: e = launch_kernel("k_stream_probe", k_stream_probe<2>, grid, block, s, a); break;
+    case 3: e = launch_kernel("k_stream_probe", k_stream_probe<3>, grid, block, s, a); break;
+    default: e = launch_kernel("k_stream_probe", k_stream_probe<4>, grid, block, s, a); break;
+    }
+    return e == hipSuccess ? MTB_OK : MTB_ERR_DEVICE;
+}

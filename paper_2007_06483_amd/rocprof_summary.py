@@ -25,10 +25,19 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2007_06483_amd", "csrc", f) for f in
 
 
 def short_name(name: str) -> str:
-    """Kernel name without namespaces, template and argument lists."""
-    n = name.split("(")[0]
+    """Kernel name without namespaces, template and argument lists
+    ("void ns::(anonymous namespace)::k<4>(ns::Args)" -> "k")."""
+    n = name.strip()
     if n.startswith("void "):
         n = n[5:]
+    if n.endswith(")") and "(" in n:
+        depth = 0
+        for i in range(len(n) - 1, -1, -1):  # the argument list's opening parenthesis
+            depth += n[i] == ")"
+            depth -= n[i] == "("
+            if depth == 0:
+                n = n[:i]
+                break
     n = n.split("<")[0]
     return n.split("::")[-1].strip() or name
 

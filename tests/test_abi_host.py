@@ -299,3 +299,15 @@ def test_quadrant_validation(mtb):
     bad = list(args)
     bad[9] = ws - 1
     assert L.mtb_align_quadrants(*bad) == 2
+
+
+def test_stream_probe_validation(mtb):
+    L = mtb.lib()
+    A, B = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    assert L.mtb_probe_stream(None, 1 << 20, B, 0, None) == 1
+    assert L.mtb_probe_stream(A, 8, B, 0, None) == 1                      # less than one 16-byte word
+    assert L.mtb_probe_stream(A, 1 << 20, B, (1 << 20) + 16, None) == 1  # writes more than it reads
+    assert L.mtb_probe_stream(A, 1 << 20, B, 1 << 17, None) == 1          # 8 bytes read per byte written
+    assert L.mtb_probe_stream(A, 1 << 20, None, 4096, None) == 1          # writes without a destination
+    assert L.mtb_probe_stream(ctypes.c_void_p(0x10004), 1 << 20, B, 0, None) == 1  # misaligned
+    assert L.mtb_probe_stream(A, 1 << 20, B, 1 << 18, None) == 4          # valid, but no device here
