@@ -412,8 +412,9 @@ typedef struct mtb_batch_item {
 
 #define MTB_MAX_BATCH 4096 /* items per mtb_align_batch call */
 
-/* Bytes of the workspace mtb_align_batch needs for these items; 0 if the
- * item list or any item is invalid. */
+/* Bytes of the workspace mtb_align_batch needs for these items (one range
+ * per stream lane, each sized for the largest group); 0 if the item list or
+ * any item is invalid. */
 size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items);
 
 /*
@@ -422,8 +423,12 @@ size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items)
  * pyramids and bitmaps, built as in mtb_build_pyramid and mtb_bitmaps).
  * Items of equal width, height, row stride and level count are processed
  * together, up to 16 pairs (32 images) per launch of each pass, with the
- * launch shape the table holds for the group's key; the groups run one after
- * another on `stream`, reusing the workspace.  The call enqueues a
+ * launch shape the table holds for the group's key.  The groups run on up to
+ * four streams of the library (created once per host thread and device, at
+ * default priority), forked from `stream` and joined back into it with
+ * events, each lane with its own range of the workspace, so that one
+ * group's latency-bound search overlaps another group's passes; work later
+ * enqueued on `stream` follows the whole batch.  The call enqueues a
  * fixed sequence of kernels (no host synchronisation, no memset), so it can be
  * captured in a HIP graph and replayed.
  *   h_items          host array of n_items items (1 .. MTB_MAX_BATCH)

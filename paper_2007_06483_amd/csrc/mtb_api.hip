@@ -556,6 +556,83 @@ constexpr int64_t kPairScratchWords =
         (kAlign / 4) +
     kTicketWords;
 
+// A batch's groups run on up to kBatchLanes streams of the library at once
+// (forked from and joined back to the caller's stream with events), each
+// lane with its own workspace range: while one group's search, a chain of
+// short latency-bound launches, leaves the device mostly idle, another
+// group's bandwidth-bound passes fill it.
+constexpr int kBatchLanes = 4;
+
+struct BatchPlan {
+    std::vector<BatchGroup> groups;
+    std::vector<int> lane;   // lane of each group
+    int lanes = 1;
+    int64_t lane_bytes = 0;  // workspace bytes of one lane (256-byte multiple)
+};
+
+BatchPlan batch_plan(const mtb_batch_item *h_items, int n_items)
+{
+    BatchPlan p;
+    p.groups = batch_groups(h_items, n_items);
+    const int ng = (int)p.groups.size();
+    p.lanes = ng < kBatchLanes ? ng : kBatchLanes;
+    std::vector<int64_t> px(ng);
+    for (int k = 0; k < ng; ++k) {
+        const mtb_batch_item &f = h_items[p.groups[k].first];
+        Geometry g;
+        make_geometry(f.width, f.height, f.levels, &g);
+        const int np = (int)p.groups[k].items.size();
+        const int64_t b = align_up(set_workspace_bytes(g, 2 * np, np), kAlign);
+        p.lane_bytes = b > p.lane_bytes ? b : p.lane_bytes;
+        px[k] = (int64_t)f.width * f.height * np;
+    }
+    // Largest groups first, each to the lane with the fewest pixels so far.
+    std::vector<int> order(ng);
+    for (int k = 0; k < ng; ++k)
+        order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return px[a] > px[b]; });
+    std::vector<int64_t> load(p.lanes, 0);
+    p.lane.assign(ng, 0);
+    for (int k : order) {
+        int best = 0;
+        for (int l = 1; l < p.lanes; ++l)
+            if (load[l] < load[best])
+                best = l;
+        p.lane[k] = best;
+        load[best] += px[k];
+    }
+    return p;
+}
+
+// The library's lane streams and events of the calling thread on the current
+// device (created once, at default priority, kept until the process ends).
+struct Lanes {
+    int device = -1;
+    hipStream_t s[kBatchLanes] = {};
+    hipEvent_t fork = nullptr, done[kBatchLanes] = {};
+};
+thread_local std::vector<Lanes> t_lanes;
+
+Lanes *batch_lanes()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return nullptr;
+    for (Lanes &l : t_lanes)
+        if (l.device == dev)
+            return &l;
+    Lanes l;
+    l.device = dev;
+    bool ok = hipEventCreateWithFlags(&l.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kBatchLanes && ok; ++i)
+        ok = hipStreamCreateWithFlags(&l.s[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&l.done[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok)
+        return nullptr;
+    t_lanes.push_back(l);
+    return &t_lanes.back();
+}
+
 // A batch: one launch set per group of items that share geometry and stride,
 // each with its key's tuned shape (or, for the key ov_key, the shape ov_shape).
 mtb_status align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range, void *d_workspace,
@@ -576,18 +653,31 @@ mtb_status align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t e
     if (cus <= 0)
         return MTB_ERR_UNSUPPORTED;
     uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
-    for (const BatchGroup &grp : batch_groups(h_items, n_items)) {
+    const BatchPlan plan = batch_plan(h_items, n_items);
+    Lanes *lanes = plan.lanes > 1 ? batch_lanes() : nullptr;
+    if (plan.lanes > 1 && !lanes)
+        return MTB_ERR_DEVICE;
+    if (lanes) {
+        if (hipEventRecord(lanes->fork, s) != hipSuccess)
+            return MTB_ERR_DEVICE;
+        for (int l = 0; l < plan.lanes; ++l)
+            if (hipStreamWaitEvent(lanes->s[l], lanes->fork, 0) != hipSuccess)
+                return MTB_ERR_DEVICE;
+    }
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < plan.groups.size() && e == hipSuccess; ++k) {
+        const BatchGroup &grp = plan.groups[k];
         const mtb_batch_item &f = h_items[grp.first];
         make_geometry(f.width, f.height, f.levels, &g);
         PairSet ps;
         int align = 16;
-        for (int k : grp.items) {
-            const mtb_batch_item &it = h_items[k];
+        for (int item : grp.items) {
+            const mtb_batch_item &it = h_items[item];
             ps.ref_img[ps.npairs] = ps.n;
             ps.rgb[ps.n++] = it.d_ref_rgb;
             ps.mov_img[ps.npairs] = ps.n;
             ps.rgb[ps.n++] = it.d_mov_rgb;
-            ps.out_row[ps.npairs++] = k;
+            ps.out_row[ps.npairs++] = item;
             const int a1 = row_alignment(it.d_ref_rgb, it.row_stride), a2 = row_alignment(it.d_mov_rgb, it.row_stride);
             align = a1 < align ? a1 : align;
             align = a2 < align ? a2 : align;
@@ -605,11 +695,18 @@ mtb_status align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t e
             t = *ov_shape;
         else
             tune_lookup(key, &t);
-        const hipError_t e = enqueue_set(ps, g, f.row_stride, align, exclude_range, ws, out, z, cus, s, false, t);
-        if (e != hipSuccess)
-            return MTB_ERR_DEVICE;
+        const int l = plan.lane[k];
+        e = enqueue_set(ps, g, f.row_stride, align, exclude_range, ws + l * plan.lane_bytes, out, z, cus,
+                        lanes ? lanes->s[l] : s, false, t);
     }
-    return MTB_OK;
+    // Join every lane back into the caller's stream, also after a failed
+    // launch, so that later work on it follows everything enqueued here.
+    bool joined = true;
+    if (lanes)
+        for (int l = 0; l < plan.lanes; ++l)
+            joined = hipEventRecord(lanes->done[l], lanes->s[l]) == hipSuccess &&
+                     hipStreamWaitEvent(s, lanes->done[l], 0) == hipSuccess && joined;
+    return e == hipSuccess && joined ? MTB_OK : MTB_ERR_DEVICE;
 }
 
 }  // namespace
@@ -1178,15 +1275,8 @@ size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items)
     for (int i = 0; i < n_items; ++i)
         if (!batch_item_valid(h_items[i], &g))
             return 0;
-    int64_t most = 0;
-    for (const BatchGroup &grp : batch_groups(h_items, n_items)) {
-        const mtb_batch_item &f = h_items[grp.first];
-        make_geometry(f.width, f.height, f.levels, &g);
-        const int np = (int)grp.items.size();
-        const int64_t b = set_workspace_bytes(g, 2 * np, np);
-        most = b > most ? b : most;
-    }
-    return (size_t)(most + kAlign);
+    const BatchPlan plan = batch_plan(h_items, n_items);
+    return (size_t)(plan.lanes * plan.lane_bytes + kAlign);
 }
 
 mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range,

@@ -201,20 +201,29 @@ def _items(mtb, specs):
     return arr
 
 
-def test_batch_workspace_is_the_largest_group(mtb):
+def test_batch_workspace_holds_one_range_per_lane(mtb):
     L = _c(mtb)
     specs = [(64, 48, 3, 192), (32, 24, 2, 96), (64, 48, 3, 192), (64, 48, 3, 256)]
     items = _items(mtb, specs)
     got = L.mtb_batch_workspace_bytes(items, len(specs))
-    # Groups: (64x48, stride 192) x2, (32x24) x1, (64x48, stride 256) x1; each
-    # group's need is at most that of its images as a stack, plus search state.
+    # Groups: (64x48, stride 192) x2, (32x24) x1, (64x48, stride 256) x1; the
+    # three groups run on three lanes, each with a range the size of the
+    # largest group's need (at most that of its images as a stack).
     two = mtb.mtb_stack_workspace_bytes(4, 64, 48, 3)
-    assert mtb.mtb_stack_workspace_bytes(2, 64, 48, 3) < got <= two + 4096
-    # 17 equal items split into 16 + 1: the workspace is that of the 16.
+    assert 3 * (mtb.mtb_stack_workspace_bytes(2, 64, 48, 3) - 256) < got <= 3 * two + 4096
+    # One group: one range.
+    one = L.mtb_batch_workspace_bytes(_items(mtb, [(64, 48, 3, 192)] * 2), 2)
+    assert one <= two + 256
+    # 17 equal items split into 16 + 1: two lanes, each sized for the 16.
     items17 = _items(mtb, [(64, 48, 3, 192)] * 17)
     items16 = _items(mtb, [(64, 48, 3, 192)] * 16)
-    assert L.mtb_batch_workspace_bytes(items17, 17) == L.mtb_batch_workspace_bytes(items16, 16)
-    assert L.mtb_batch_workspace_bytes(items16, 16) > L.mtb_batch_workspace_bytes(items16, 8)
+    w16 = L.mtb_batch_workspace_bytes(items16, 16)
+    assert L.mtb_batch_workspace_bytes(items17, 17) == 2 * (w16 - 256) + 256
+    assert w16 > L.mtb_batch_workspace_bytes(items16, 8)
+    # At most four lanes: five groups of different sizes take four ranges.
+    five = _items(mtb, [(64 + 8 * k, 48, 3, 3 * (64 + 8 * k)) for k in range(5)])
+    big = L.mtb_batch_workspace_bytes(_items(mtb, [(96, 48, 3, 288)]), 1)
+    assert L.mtb_batch_workspace_bytes(five, 5) == 4 * (big - 256) + 256
 
 
 def test_batch_validation(mtb):
