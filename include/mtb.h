@@ -184,7 +184,7 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
  * mtb_align_pair without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the search state (counters, bases,
- * coarse surfaces, tickets; at most 10760 bytes, enough for MTB_MAX_LEVELS
+ * coarse surfaces, tickets; at most 30720 bytes, enough for MTB_MAX_LEVELS
  * levels) lives in a static device array of the library, one per device,
  * held until the process ends.  The call allocates nothing (no hipMalloc,
  * hipFree or allocating library routine); it clears the array with a kernel
@@ -264,8 +264,11 @@ mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int
  *   - the bitmaps pass: workgroups as a percentage of one resident round, and
  *     wavefronts per workgroup (2, 4 or 8);
  *   - the search: how many of the coarsest levels are searched over
- *     exhaustive windows (-1: the built-in rule; 0..3; the results are the
- *     same either way), and per fine level the rows each row stream covers
+ *     exhaustive windows (radius 1, 3, 7, 15, 31 from the coarsest down;
+ *     -1: the built-in rule, up to three levels of at most 8192 words of
+ *     32 bits, and a fourth and fifth while the launch's window cells times
+ *     words stay within 2^25; 0..5; the results are the same either way),
+ *     and per fine level the rows each row stream covers
  *     and the lanes of a row stream (8, 16, 32 or 64; 0: the built-in rules,
  *     the fewest rows that keep one level's grid within one resident round
  *     and the width that pads rows least).
@@ -283,7 +286,7 @@ typedef struct mtb_launch_shape {
     int32_t pyramid_tile_group; /* 1, 2 or 4 (default 1) */
     int32_t bitmaps_blocks_pct; /* 25 .. 100 (default 100) */
     int32_t bitmaps_waves;      /* 2, 4 or 8 (default 4) */
-    int32_t coarse_levels;      /* -1 (rule), 0 .. 3 */
+    int32_t coarse_levels;      /* -1 (rule), 0 .. 5 */
     int32_t search_rows[16];    /* per level: 0, or a multiple of 4 in 4 .. 64 */
     int32_t search_lanes[16];   /* per level: 0, 8, 16, 32 or 64 */
     float step_ms;              /* tuners: median time of one call with this shape */

@@ -417,7 +417,7 @@ mtb_status tune_one(const Geometry &g, int npairs, int cus, hipStream_t s, Run r
         consider(c);
     }
     if (npairs > 0) {
-        const int rule = coarse_level_count(g);
+        const int rule = coarse_level_count(g, npairs);
         const int most = g.L < kCoarseLevels ? g.L : kCoarseLevels;
         for (int cn : {rule - 1, rule + 1}) {
             if (cn < 0 || cn > most)
@@ -426,7 +426,7 @@ mtb_status tune_one(const Geometry &g, int npairs, int cus, hipStream_t s, Run r
             c.coarse = cn;
             consider(c);
         }
-        for (int l = g.L - 1 - coarse_levels_used(g, &best); l >= 0; --l) {
+        for (int l = g.L - 1 - coarse_levels_used(g, npairs, &best); l >= 0; --l) {
             for (int cw : {3, 4, 5, 6}) {
                 LaunchTune c = best;
                 c.cw[l] = cw;

@@ -109,9 +109,12 @@ struct BitmapArgs {
 
 // The coarsest levels (at most kCoarseLevels) are searched exhaustively over
 // every shift the coarse-to-fine search could reach there: radius 2^(i+1) - 1
-// at the i-th coarsest level.  Their error surfaces take kSurfWords words.
-constexpr int kCoarseLevels = 3;
-constexpr int kSurfWords = 3 * 3 + 7 * 7 + 15 * 15;
+// at the i-th coarsest level.  Their error surfaces take kSurfWords words; the
+// first kLdsSurfWords (the windows of radius 1, 3 and 7) are staged in LDS by
+// the walk, the larger ones read from memory.
+constexpr int kCoarseLevels = 5;
+constexpr int kSurfWords = 3 * 3 + 7 * 7 + 15 * 15 + 31 * 31 + 63 * 63;
+constexpr int kLdsSurfWords = 3 * 3 + 7 * 7 + 15 * 15;
 
 // Per pair the search state is: counters uint32[L][kCounterWords], then
 // base int32[L][2] (the centre of each level's nine candidates), then the
@@ -235,15 +238,15 @@ hipError_t launch_chain(int32_t *d_shifts, int n, int ref, hipStream_t s);
 hipError_t launch_quadrant_flag(const int32_t *d_shifts, int32_t tol, int32_t *d_flag, hipStream_t s);
 // Searches every level of every pair and writes a.out; a.state and *a.done
 // must be zero.
-// Levels L-1 .. L-coarse_level_count(g) are searched exhaustively; the others
-// are the fine levels.
-int coarse_level_count(const Geometry &g);
+// Levels L-1 .. L-coarse_level_count(g, npairs) are searched exhaustively;
+// the others are the fine levels.
+int coarse_level_count(const Geometry &g, int npairs);
 // Rows per stream launch_search uses at fine level l without a tuned value
 // (for a stream width cw_log2, 0: the rule).
 int search_rows_rule(const Geometry &g, int l, int npairs, int device_cus, int cw_log2 = 0);
 int search_row_blocks(const Geometry &g, int l, int rows, int cw_log2 = 0);
 // Coarse levels a search runs with shape t (null: the rule).
-int coarse_levels_used(const Geometry &g, const LaunchTune *t);
+int coarse_levels_used(const Geometry &g, int npairs, const LaunchTune *t);
 // t: the launch shape (rows and lanes per stream per level, coarse levels), or null for the rules.
 hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s, const LaunchTune *t = nullptr);
 

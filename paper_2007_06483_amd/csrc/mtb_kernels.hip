@@ -1134,7 +1134,10 @@ __device__ __forceinline__ uint32_t *pair_surface(const SearchArgs &a, int p)
 // Radius of the exhaustive window at the i-th coarsest level, and where its
 // (2R+1)^2 surface starts.
 __host__ __device__ __forceinline__ int coarse_radius(int i) { return (2 << i) - 1; }
-__device__ __forceinline__ int coarse_surface_offset(int i) { return i == 0 ? 0 : (i == 1 ? 9 : 58); }
+__device__ __forceinline__ int coarse_surface_offset(int i)
+{
+    return i == 0 ? 0 : i == 1 ? 9 : i == 2 ? 58 : i == 3 ? 283 : 1244;
+}
 
 // Records level l's nine errors and chosen shift in pair p's output row.
 __device__ __forceinline__ void write_level(const SearchArgs &a, int p, int l, const uint32_t *c, int sx, int sy)
@@ -1241,21 +1244,26 @@ __host__ __device__ __forceinline__ int coarse_slabs(const LevelGeom &lv)
     return (lv.h + rows - 1) / rows;
 }
 
-// Walks pair p's coarse error surfaces (in `surf`) from the coarsest level
-// down, testing the same nine candidates in the same order, with the same
-// tie-break, as the nine-candidate search; records each level's outputs when
-// `write` is set.  Returns the shift chosen at the finest coarse level.
+// Walks pair p's coarse error surfaces from the coarsest level down, testing
+// the same nine candidates in the same order, with the same tie-break, as the
+// nine-candidate search; records each level's outputs when `write` is set.
+// The windows of radius 1, 3 and 7 are read from `surf` (their LDS copy), the
+// larger ones from the pair's surfaces in memory.  Returns the shift chosen at
+// the finest coarse level.
 __device__ int2 coarse_walk(const SearchArgs &a, int p, const uint32_t *surf, bool write)
 {
     int bx = 0, by = 0, sx = 0, sy = 0;
     for (int i = 0; i < a.coarse_n; ++i) {
         const int R = coarse_radius(i), side = 2 * R + 1;
-        const uint32_t *w = surf + coarse_surface_offset(i);
+        const bool lds = coarse_surface_offset(i) < kLdsSurfWords;
+        const uint32_t *w = (lds ? surf : pair_surface(a, p)) + coarse_surface_offset(i);
         uint32_t c[9];
         // |bx|, |by| <= 2^(i+1) - 2 here, so every candidate lies in the window.
         for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx)
-                c[(dy + 1) * 3 + dx + 1] = w[(by + dy + R) * side + (bx + dx + R)];
+            for (int dx = -1; dx <= 1; ++dx) {
+                const uint32_t *cell = w + (by + dy + R) * side + (bx + dx + R);
+                c[(dy + 1) * 3 + dx + 1] = lds ? *cell : load_shared(cell);
+            }
         const int best = argmin9(c);
         sx = bx + best % 3 - 1;
         sy = by + best / 3 - 1;
@@ -1274,24 +1282,17 @@ __device__ int2 coarse_walk(const SearchArgs &a, int p, const uint32_t *surf, bo
 // cx = -R..R) over one slab of rows into the pair's error surface.  The first
 // fine level walks the surfaces; when every level is coarse, the last
 // workgroup to finish walks them here and writes the outputs.
-__global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
+// The errors of one coarse item for every cx of its window row, added into
+// the pair's error surface; kMaxR bounds the window radius R (7 or 31): words
+// k-1 .. k+1 of a moving row hold every shift |cx| <= 31 of word k.
+template <int kMaxR>
+__device__ __forceinline__ void coarse_score(const SearchArgs &a, int pair, int i, int item)
 {
-    constexpr int kMaxR = 7;
     constexpr int kRows = kCoarseRows;
     __shared__ uint32_t red[4][2 * kMaxR + 1];
-    const int pair = blockIdx.y;
     const int wave = wave_id();
     const int lane = threadIdx.x & 63;
     const Geometry &g = a.g;
-
-    int item = blockIdx.x, i = 0;
-    for (;;) {
-        const int cnt = (2 * coarse_radius(i) + 1) * coarse_slabs(g.lv[g.L - 1 - i]);
-        if (item < cnt)
-            break;
-        item -= cnt;
-        ++i;
-    }
     const LevelGeom &lv = g.lv[g.L - 1 - i];
     const int R = coarse_radius(i);
     const int slabs = coarse_slabs(lv);
@@ -1314,9 +1315,8 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
     for (int c = 0; c < 2 * kMaxR + 1; ++c)
         acc[c] = 0u;
     for (int k = col; k < n32; k += cw) {
-        // Words k-1 .. k+1 of moving row y - cy hold every shift |cx| <= 7 of
-        // word k.  Rows and columns outside the level are read clamped (or
-        // from the neighbouring row) and their exclusion words masked below.
+        // Rows and columns outside the level are read clamped (or from the
+        // neighbouring row) and their exclusion words masked below.
         const uint32_t cm0 = k >= 1 ? ~0u : 0u, cm2 = k + 1 < n32 ? ~0u : 0u;
         uint32_t t[kRows], e[kRows], mt[kRows][3], me[kRows][3];
 #pragma unroll
@@ -1366,19 +1366,41 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
         if (v)
             atomicAdd(surf + (cy + R) * (2 * R + 1) + threadIdx.x, v);
     }
+}
+
+// kMaxR: the largest window radius of the launch (7 for up to three coarse
+// levels, 31 for five), which sizes the per-lane sums.
+template <int kMaxR>
+__global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
+{
+    const int pair = blockIdx.y;
+    const Geometry &g = a.g;
+    int item = blockIdx.x, i = 0;
+    for (;;) {
+        const int cnt = (2 * coarse_radius(i) + 1) * coarse_slabs(g.lv[g.L - 1 - i]);
+        if (item < cnt)
+            break;
+        item -= cnt;
+        ++i;
+    }
+    if (kMaxR == 7 || coarse_radius(i) <= 7)
+        coarse_score<7>(a, pair, i, item);
+    else
+        coarse_score<kMaxR>(a, pair, i, item);
 
     if (a.coarse_n < g.L || !last_workgroup(a.done))
         return;
-    // Every level is coarse: walk all pairs' surfaces, fetched at once.
+    // Every level is coarse: walk all pairs' surfaces, the small windows
+    // fetched into LDS at once.
     constexpr int kLoads = 8;
-    __shared__ uint32_t ssurf[kMaxStack * kSurfWords];
-    const int words = a.npairs * kSurfWords;
+    __shared__ uint32_t ssurf[kMaxStack * kLdsSurfWords];
+    const int words = a.npairs * kLdsSurfWords;
     for (int q0 = 0; q0 < words; q0 += 256 * kLoads) {
         uint32_t v[kLoads];
 #pragma unroll
         for (int u = 0; u < kLoads; ++u) {
             const int q = q0 + u * 256 + (int)threadIdx.x;
-            v[u] = q < words ? load_shared(pair_surface(a, q / kSurfWords) + q % kSurfWords) : 0u;
+            v[u] = q < words ? load_shared(pair_surface(a, q / kLdsSurfWords) + q % kLdsSurfWords) : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kLoads; ++u) {
@@ -1389,7 +1411,7 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
     }
     __syncthreads();
     if ((int)threadIdx.x < a.npairs)
-        coarse_walk(a, threadIdx.x, ssurf + threadIdx.x * kSurfWords, true);
+        coarse_walk(a, threadIdx.x, ssurf + threadIdx.x * kLdsSurfWords, true);
 }
 
 // This level's base (twice the winner of the level above, or the coarse walk's
@@ -1397,7 +1419,7 @@ __global__ __launch_bounds__(256) void k_search_coarse(SearchArgs a)
 // every thread of the workgroup; ends with a workgroup barrier.
 __device__ __forceinline__ void level_base(const SearchArgs &a, int pair, int *sbase)
 {
-    __shared__ uint32_t cnt[kSurfWords > kCounterWords ? kSurfWords : kCounterWords];
+    __shared__ uint32_t cnt[kLdsSurfWords > kCounterWords ? kLdsSurfWords : kCounterWords];
     __shared__ uint32_t tot[9];
     __shared__ int sprev[2];
     const Geometry &g = a.g;
@@ -1412,12 +1434,12 @@ __device__ __forceinline__ void level_base(const SearchArgs &a, int pair, int *s
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int q = u * 256 + (int)threadIdx.x;
-            v[u] = q < kSurfWords ? surf[q] : 0u;
+            v[u] = q < kLdsSurfWords ? surf[q] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int q = u * 256 + (int)threadIdx.x;
-            if (q < kSurfWords)
+            if (q < kLdsSurfWords)
                 cnt[q] = v[u];
         }
         __syncthreads();
@@ -1864,14 +1886,29 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s, int block
 }
 
 // The i-th coarsest level is searched exhaustively when i < kCoarseLevels and
-// its window rows stay cheap for one workgroup: at most this many dwords.
+// its window rows stay cheap for one workgroup: at most kCoarseDwords dwords.
+// The windows of radius 15 and 31 (i = 3, 4) also have to keep the launch's
+// work (window cells x dwords, over all pairs) within kCoarseWork: a small
+// pair then searches every level in this one launch instead of a chain of
+// fine launches, while large images keep the nine-candidate search there.
 constexpr int64_t kCoarseDwords = 8192;
+constexpr int64_t kCoarseWork = (int64_t)1 << 25;
 
-int coarse_level_count(const Geometry &g)
+int coarse_level_count(const Geometry &g, int npairs)
 {
     int cn = 0;
-    while (cn < kCoarseLevels && cn < g.L && (int64_t)2 * g.lv[g.L - 1 - cn].wpr * g.lv[g.L - 1 - cn].h <= kCoarseDwords)
+    int64_t work = 0;
+    while (cn < kCoarseLevels && cn < g.L) {
+        const LevelGeom &lv = g.lv[g.L - 1 - cn];
+        const int64_t dwords = (int64_t)2 * lv.wpr * lv.h;
+        if (dwords > kCoarseDwords)
+            break;
+        const int64_t side = 2 * coarse_radius(cn) + 1;
+        work += side * side * dwords * (npairs > 0 ? npairs : 1);
+        if (cn >= 3 && work > kCoarseWork)
+            break;
         ++cn;
+    }
     return cn;
 }
 
@@ -1898,10 +1935,10 @@ int search_rows_rule(const Geometry &g, int l, int npairs, int cus, int cw_log2)
     return rows;
 }
 
-int coarse_levels_used(const Geometry &g, const LaunchTune *t)
+int coarse_levels_used(const Geometry &g, int npairs, const LaunchTune *t)
 {
     if (!t || t->coarse < 0)
-        return coarse_level_count(g);
+        return coarse_level_count(g, npairs);
     const int most = g.L < kCoarseLevels ? g.L : kCoarseLevels;
     return t->coarse < most ? t->coarse : most;
 }
@@ -1909,14 +1946,15 @@ int coarse_levels_used(const Geometry &g, const LaunchTune *t)
 hipError_t launch_search(SearchArgs a, int cus, hipStream_t s, const LaunchTune *t)
 {
     const Geometry &g = a.g;
-    const int cn = coarse_levels_used(g, t);
+    const int cn = coarse_levels_used(g, a.npairs, t);
     a.coarse_n = cn;
     hipError_t e = hipSuccess;
     if (cn > 0) {
         int items = 0;
         for (int i = 0; i < cn; ++i)
             items += (2 * coarse_radius(i) + 1) * coarse_slabs(g.lv[g.L - 1 - i]);
-        e = launch_kernel("k_search_coarse", k_search_coarse, dim3(items, a.npairs), dim3(256), s, a);
+        e = launch_kernel("k_search_coarse", cn > 3 ? k_search_coarse<31> : k_search_coarse<7>, dim3(items, a.npairs),
+                          dim3(256), s, a);
         if (e != hipSuccess)
             return e;
     }

@@ -305,3 +305,21 @@ def test_full_size_stack_7x6000x4000(mtb):
     w = synth.workload("stack7_6000x4000")
     (imgs, _, ref), = w.stacks
     _check_stack(mtb, imgs, w.levels, ref_index=ref)
+
+
+def test_small_pair_searches_every_level_in_one_launch(mtb):
+    # A 512x384 pair's five levels fit the exhaustive windows' work budget
+    # (radius 1 .. 31 from the coarsest down): the search is one zeroing and
+    # one coarse launch, and every level's nine errors still equal the oracle's.
+    (imgs, _, _), = synth.workload("pair_512x384").stacks
+    ref, mov = imgs
+    h, w, _ = ref.shape
+    br = mtb.mtb_bitmaps(mtb.mtb_build_pyramid(_to_dev(ref), 5), w, h, 5)
+    bmv = mtb.mtb_bitmaps(mtb.mtb_build_pyramid(_to_dev(mov), 5), w, h, 5)
+    torch.cuda.synchronize()
+    mtb.mtb_profile_begin(None)
+    mtb.mtb_align_pair(br, bmv, w, h, 5)
+    torch.cuda.synchronize()
+    launches = {k: c for k, (c, _) in mtb.mtb_profile_end().items()}
+    assert launches == {"k_zero": 1, "k_search_coarse": 1}, launches
+    _check_pair(mtb, ref, mov, 5)

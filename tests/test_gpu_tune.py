@@ -1,6 +1,6 @@
 """Launch shapes never change results: the tuner's choice and explicit shapes
 (pyramid and bitmap grids from a quarter to four rounds, pyramid tile groups
-of 1, 2 and 4, 2 to 8 wavefronts per bitmaps workgroup, 0 to 3 exhaustive
+of 1, 2 and 4, 2 to 8 wavefronts per bitmaps workgroup, 0 to 5 exhaustive
 coarse levels, every fine level's rows per stream from 4 to 64 and stream
 widths of 8 to 64 lanes) give bit-identical shifts, errors and traces, equal
 to the oracle's.  Tuned shapes survive a save and load; batch groups are
@@ -51,7 +51,7 @@ def test_tuned_shape_keeps_results_and_is_stored(mtb):
     shape = mtb.mtb_tune_stack(d, L)
     assert 25 <= shape["pyramid_slots_pct"] <= 400 and 25 <= shape["bitmaps_blocks_pct"] <= 100
     assert shape["pyramid_tile_group"] in (1, 2, 4) and shape["bitmaps_waves"] in (2, 4, 8)
-    assert -1 <= shape["coarse_levels"] <= 3
+    assert -1 <= shape["coarse_levels"] <= 5
     assert all(w in (0, 8, 16, 32, 64) for w in shape["search_lanes"])
     assert all(r == 0 or (r % 4 == 0 and 4 <= r <= 64) for r in shape["search_rows"])
     assert shape["step_ms"] > 0 and shape["default_ms"] > 0
@@ -70,7 +70,8 @@ def test_tuned_shape_keeps_results_and_is_stored(mtb):
 
 
 @pytest.mark.parametrize("pyr,grp,bm,waves,coarse", [(25, 1, 25, 2, -1), (50, 2, 100, 8, 0), (200, 4, 50, 4, 3),
-                                                    (400, 1, 100, 8, 1), (100, 4, 75, 2, 2)])
+                                                    (400, 1, 100, 8, 1), (100, 4, 75, 2, 2), (100, 1, 100, 4, 4),
+                                                    (100, 2, 100, 4, 5)])
 def test_explicit_shapes_give_identical_results(mtb, pyr, grp, bm, waves, coarse):
     imgs, d = _stack(4, 1100, 700, 62, 30)
     L = 6

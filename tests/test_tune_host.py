@@ -39,7 +39,7 @@ def test_set_lookup_and_reset():
     {"pyramid_slots_pct": 24}, {"pyramid_slots_pct": 401}, {"bitmaps_blocks_pct": 24},
     {"bitmaps_blocks_pct": 101}, {"search_rows": [2]}, {"search_rows": [6]}, {"search_rows": [68]},
     {"search_rows": [0, -4]}, {"pyramid_tile_group": 3}, {"pyramid_tile_group": 0}, {"bitmaps_waves": 1},
-    {"bitmaps_waves": 16}, {"coarse_levels": -2}, {"coarse_levels": 4}, {"search_lanes": [4]},
+    {"bitmaps_waves": 16}, {"coarse_levels": -2}, {"coarse_levels": 6}, {"search_lanes": [4]},
     {"search_lanes": [0, 128]}, {"search_lanes": [24]},
 ])
 def test_out_of_range_shapes_are_refused(bad):
