@@ -754,7 +754,7 @@ def main():
     shape = None
     if args.shape and not bytemaps:
         full = {"pyramid_slots_pct": 100, "pyramid_tile_group": 1, "bitmaps_blocks_pct": 100, "bitmaps_waves": 4,
-                "coarse_levels": -1, "search_rows": [], "search_lanes": []}
+                "coarse_levels": -1, "small_search": -1, "search_rows": [], "search_lanes": []}
         full.update(json.loads(args.shape))
         mtb.mtb_set_shape(n, W, H, int(d_imgs[0].stride(0)), L, full)
         shape = dict(mtb.mtb_tuned_shape(n, W, H, int(d_imgs[0].stride(0)), L), step_ms=0.0, default_ms=0.0)
@@ -890,12 +890,13 @@ def main():
         "e2e_incl_h2d": {"ms_per_step": round(e2e_ms, 3), "MPps": round(mp_total / (e2e_ms / 1e3), 1)},
         "launch_shape": {"tuned": False, "pyramid_slots_pct": 100, "pyramid_tile_group": 1,
                          "bitmaps_blocks_pct": 100, "bitmaps_waves": 4, "coarse_levels": "built-in rule",
-                         "search_rows": "built-in rule", "search_lanes": "built-in rule"}
+                         "small_search": "built-in rule", "search_rows": "built-in rule",
+                         "search_lanes": "built-in rule"}
         if shape is None else {
             "tuned": bool(args.tune), "pyramid_slots_pct": shape["pyramid_slots_pct"],
             "pyramid_tile_group": shape["pyramid_tile_group"], "bitmaps_blocks_pct": shape["bitmaps_blocks_pct"],
             "bitmaps_waves": shape["bitmaps_waves"], "coarse_levels": shape["coarse_levels"],
-            "search_rows": shape["search_rows"][:L], "search_lanes": shape["search_lanes"][:L],
+            "small_search": shape["small_search"], "search_rows": shape["search_rows"][:L], "search_lanes": shape["search_lanes"][:L],
             "tuner_step_ms": round(shape["step_ms"], 4), "tuner_default_ms": round(shape["default_ms"], 4)},
     }
 

@@ -166,6 +166,10 @@ mtb_status mtb_bitmaps(const void *d_pyramid, int32_t width, int32_t height, int
  * with (S_c B)[y][x] = B[y - cy][x - cx], zero where that falls outside the
  * image.  The lowest error wins, ties going to the lowest (ddy, ddx)
  * (ddy-major order); the next level's base is twice the winner.
+ * A pair whose two bitmaps buffers' planes fit 144 KiB is searched by one
+ * workgroup in one launch that leaves the workspace untouched; larger pairs
+ * take a zeroing launch, the coarse levels' launch and one launch per finer
+ * level, with their counters in the workspace.
  *   d_bm_ref, d_bm_mov   bitmaps buffers written by mtb_bitmaps
  *   d_workspace          >= mtb_pair_workspace_bytes(levels) bytes, contents ignored
  *   d_shift              int32[2] receives (dx, dy) at level 0
@@ -188,7 +192,8 @@ mtb_status mtb_align_pair(const void *d_bm_ref, const void *d_bm_mov, int32_t wi
  * levels) lives in a static device array of the library, one per device,
  * held until the process ends.  The call allocates nothing (no hipMalloc,
  * hipFree or allocating library routine); it clears the array with a kernel
- * before the search.  Every call on a device shares that device's array and
+ * before the search (a pair searched by one workgroup, as in mtb_align_pair,
+ * neither clears nor uses it).  Every call on a device shares that device's array and
  * leaves its last contents there: calls that overlap on one device (on
  * different streams or host threads) race and must be ordered by the caller.
  * Arguments, results and errors as for mtb_align_pair, minus the workspace;
@@ -271,7 +276,11 @@ mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int
  *     and per fine level the rows each row stream covers
  *     and the lanes of a row stream (8, 16, 32 or 64; 0: the built-in rules,
  *     the fewest rows that keep one level's grid within one resident round
- *     and the width that pads rows least).
+ *     and the width that pads rows least); and whether a pair whose two
+ *     bitmap pyramids fit 144 KiB (every plane of the bitmaps buffer, from
+ *     the end of its leading 256-byte guard to the medians) is searched by one
+ *     workgroup that holds both in LDS and runs every level in one launch
+ *     (-1 or 1, the default) or by the launches above (0).
  * Shapes are kept per key (n images, width, height, levels, and whether
  * row_stride is a multiple of 16, else of 4, else neither) in a process-wide
  * table guarded by a mutex.  A key without a shape of its own uses the shape
@@ -287,6 +296,7 @@ typedef struct mtb_launch_shape {
     int32_t bitmaps_blocks_pct; /* 25 .. 100 (default 100) */
     int32_t bitmaps_waves;      /* 2, 4 or 8 (default 4) */
     int32_t coarse_levels;      /* -1 (rule), 0 .. 5 */
+    int32_t small_search;       /* -1 or 1: one workgroup per pair where it fits, 0: never */
     int32_t search_rows[16];    /* per level: 0, or a multiple of 4 in 4 .. 64 */
     int32_t search_lanes[16];   /* per level: 0, 8, 16, 32 or 64 */
     float step_ms;              /* tuners: median time of one call with this shape */
@@ -298,7 +308,9 @@ typedef struct mtb_launch_shape {
  * alignments (median of 7 after a warm-up, HIP events on `stream`) under the
  * built-in shape and under candidates changed one knob at a time (pyramid
  * 50/75/150/200 %, tile groups of 2 and 4, bitmaps 50/75 %, 2 and 8
- * wavefronts, one coarse level fewer or more, and at each fine level every
+ * wavefronts, the search by the launches above where one workgroup would
+ * take the pair, and unless one workgroup searches: one coarse level fewer
+ * or more, and at each fine level every
  * stream width and the rows halved or doubled), keeps a change only if it is
  * at least 2 % faster, stores the result in the table and writes it to
  * *h_out.  Arguments as for mtb_align_stack; d_shifts and d_errs receive the

@@ -119,13 +119,14 @@ class _KernelTime(ctypes.Structure):
 class _LaunchShape(ctypes.Structure):
     _fields_ = [("pyramid_slots_pct", ctypes.c_int32), ("pyramid_tile_group", ctypes.c_int32),
                 ("bitmaps_blocks_pct", ctypes.c_int32), ("bitmaps_waves", ctypes.c_int32),
-                ("coarse_levels", ctypes.c_int32), ("search_rows", ctypes.c_int32 * MTB_MAX_LEVELS),
+                ("coarse_levels", ctypes.c_int32), ("small_search", ctypes.c_int32),
+                ("search_rows", ctypes.c_int32 * MTB_MAX_LEVELS),
                 ("search_lanes", ctypes.c_int32 * MTB_MAX_LEVELS), ("step_ms", ctypes.c_float),
                 ("default_ms", ctypes.c_float)]
 
 
 _SHAPE_DEFAULTS = {"pyramid_slots_pct": 100, "pyramid_tile_group": 1, "bitmaps_blocks_pct": 100,
-                   "bitmaps_waves": 4, "coarse_levels": -1}
+                   "bitmaps_waves": 4, "coarse_levels": -1, "small_search": -1}
 
 
 def _shape_dict(c: _LaunchShape) -> dict:
@@ -140,7 +141,7 @@ def _shape_struct(d: dict) -> _LaunchShape:
     lanes = list(d.get("search_lanes", [])) + [0] * MTB_MAX_LEVELS
     v = {k: int(d.get(k, dv)) for k, dv in _SHAPE_DEFAULTS.items()}
     return _LaunchShape(v["pyramid_slots_pct"], v["pyramid_tile_group"], v["bitmaps_blocks_pct"],
-                        v["bitmaps_waves"], v["coarse_levels"],
+                        v["bitmaps_waves"], v["coarse_levels"], v["small_search"],
                         (ctypes.c_int32 * MTB_MAX_LEVELS)(*rows[:MTB_MAX_LEVELS]),
                         (ctypes.c_int32 * MTB_MAX_LEVELS)(*lanes[:MTB_MAX_LEVELS]), 0.0, 0.0)
 

@@ -296,6 +296,8 @@ bool shape_valid(const mtb_launch_shape &s)
         return false;
     if (s.coarse_levels < -1 || s.coarse_levels > kCoarseLevels)
         return false;
+    if (s.small_search < -1 || s.small_search > 1)
+        return false;
     for (int l = 0; l < kMaxLevels; ++l) {
         const int r = s.search_rows[l], w = s.search_lanes[l];
         if (r != 0 && (r < kRowsStep || r > kRowsMax || r % kRowsStep != 0))
@@ -314,6 +316,7 @@ LaunchTune from_shape(const mtb_launch_shape &s)
     t.bm_pct = s.bitmaps_blocks_pct;
     t.bm_waves = s.bitmaps_waves;
     t.coarse = s.coarse_levels;
+    t.small = s.small_search;
     for (int l = 0; l < kMaxLevels; ++l) {
         t.rows[l] = s.search_rows[l];
         const int w = s.search_lanes[l];
@@ -330,6 +333,7 @@ void to_shape(const LaunchTune &t, mtb_launch_shape *s)
     s->bitmaps_blocks_pct = t.bm_pct;
     s->bitmaps_waves = t.bm_waves;
     s->coarse_levels = t.coarse;
+    s->small_search = t.small;
     for (int l = 0; l < kMaxLevels; ++l) {
         s->search_rows[l] = t.rows[l];
         s->search_lanes[l] = t.cw[l] ? 1 << t.cw[l] : 0;
@@ -416,7 +420,12 @@ mtb_status tune_one(const Geometry &g, int npairs, int cus, hipStream_t s, Run r
         c.bm_waves = w;
         consider(c);
     }
-    if (npairs > 0) {
+    if (npairs > 0 && small_search_fits(g)) {
+        LaunchTune c = best;
+        c.small = 0;
+        consider(c);
+    }
+    if (npairs > 0 && !small_search_used(g, &best)) {
         const int rule = coarse_level_count(g, npairs);
         const int most = g.L < kCoarseLevels ? g.L : kCoarseLevels;
         for (int cn : {rule - 1, rule + 1}) {
@@ -522,13 +531,17 @@ mtb_status align_pair_in(const void *d_bm_ref, const void *d_bm_mov, const Geome
 {
     const int levels = g.L;
 
-    ZeroArgs z;
-    memset(&z, 0, sizeof(z));
-    z.ptr[0] = state;
-    z.words[0] = state_stride_words(levels) + kTicketWords;  // counters, bases, surfaces, tickets
-    z.count = 1;
-    if (launch_zero(z, s) != hipSuccess)
-        return MTB_ERR_DEVICE;
+    // The one-workgroup search keeps no state in memory; the others count
+    // into zeroed counters.
+    if (!small_search_used(g, nullptr)) {
+        ZeroArgs z;
+        memset(&z, 0, sizeof(z));
+        z.ptr[0] = state;
+        z.words[0] = state_stride_words(levels) + kTicketWords;  // counters, bases, surfaces, tickets
+        z.count = 1;
+        if (launch_zero(z, s) != hipSuccess)
+            return MTB_ERR_DEVICE;
+    }
 
     SearchArgs a;
     memset(&a, 0, sizeof(a));
@@ -1156,12 +1169,12 @@ mtb_status mtb_tune_save(const char *path)
     if (!f)
         return MTB_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
-    bool ok = fprintf(f, "mtb-tune 1 %s\n", platform.c_str()) > 0;
+    bool ok = fprintf(f, "mtb-tune 2 %s\n", platform.c_str()) > 0;
     for (const auto &kv : g_tune_table) {
         const TuneKey &k = kv.first;
         const LaunchTune &t = kv.second;
-        ok = ok && fprintf(f, "%d %d %d %d %d  %d %d %d %d %d ", k.n, k.w, k.h, k.levels, k.align, t.pyr_pct,
-                           t.pyr_group_log2, t.bm_pct, t.bm_waves, t.coarse) > 0;
+        ok = ok && fprintf(f, "%d %d %d %d %d  %d %d %d %d %d %d ", k.n, k.w, k.h, k.levels, k.align, t.pyr_pct,
+                           t.pyr_group_log2, t.bm_pct, t.bm_waves, t.coarse, t.small) > 0;
         for (int l = 0; l < kMaxLevels && ok; ++l)
             ok = fprintf(f, " %d", t.rows[l]) > 0;
         for (int l = 0; l < kMaxLevels && ok; ++l)
@@ -1187,14 +1200,14 @@ mtb_status mtb_tune_load(const char *path, int32_t *h_loaded)
     std::vector<std::pair<TuneKey, LaunchTune>> got;
     bool ok = fgets(line, sizeof(line), f) != nullptr;
     // Shapes tuned on another architecture or HIP runtime are skipped whole.
-    const bool same = ok && std::string(line) == "mtb-tune 1 " + platform + "\n";
+    const bool same = ok && std::string(line) == "mtb-tune 2 " + platform + "\n";
     while (ok && same && fgets(line, sizeof(line), f)) {
         TuneKey k;
         LaunchTune t;
         int used = 0;
         const char *p = line;
-        ok = sscanf(p, "%d %d %d %d %d %d %d %d %d %d%n", &k.n, &k.w, &k.h, &k.levels, &k.align, &t.pyr_pct,
-                    &t.pyr_group_log2, &t.bm_pct, &t.bm_waves, &t.coarse, &used) == 10;
+        ok = sscanf(p, "%d %d %d %d %d %d %d %d %d %d %d%n", &k.n, &k.w, &k.h, &k.levels, &k.align, &t.pyr_pct,
+                    &t.pyr_group_log2, &t.bm_pct, &t.bm_waves, &t.coarse, &t.small, &used) == 11;
         p += used;
         for (int l = 0; l < 2 * kMaxLevels && ok; ++l) {
             ok = sscanf(p, "%d%n", l < kMaxLevels ? &t.rows[l] : &t.cw[l - kMaxLevels], &used) == 1;

@@ -218,6 +218,7 @@ struct LaunchTune {
     int32_t bm_pct = 100;
     int32_t bm_waves = 4;
     int32_t coarse = -1;
+    int32_t small = -1;   // one-workgroup search where a pair fits LDS: -1 or 1 yes, 0 never
     int32_t rows[kMaxLevels] = {};
     int32_t cw[kMaxLevels] = {};
 };
@@ -237,7 +238,7 @@ hipError_t launch_chain(int32_t *d_shifts, int n, int ref, hipStream_t s);
 // d_flag[0] = 1 if two of the four shifts differ by more than tol along an axis.
 hipError_t launch_quadrant_flag(const int32_t *d_shifts, int32_t tol, int32_t *d_flag, hipStream_t s);
 // Searches every level of every pair and writes a.out; a.state and *a.done
-// must be zero.
+// must be zero unless small_search_used(a.g, t).
 // Levels L-1 .. L-coarse_level_count(g, npairs) are searched exhaustively;
 // the others are the fine levels.
 int coarse_level_count(const Geometry &g, int npairs);
@@ -247,6 +248,13 @@ int search_rows_rule(const Geometry &g, int l, int npairs, int device_cus, int c
 int search_row_blocks(const Geometry &g, int l, int rows, int cw_log2 = 0);
 // Coarse levels a search runs with shape t (null: the rule).
 int coarse_levels_used(const Geometry &g, int npairs, const LaunchTune *t);
+// A pair whose two bitmap pyramids (every plane, as laid out in the bitmaps
+// buffer) fit kSmallLdsBytes is searched by one workgroup that holds both in
+// LDS and runs every level (k_search_small): one launch, no search state.
+constexpr int64_t kSmallLdsBytes = 144 * 1024;
+bool small_search_fits(const Geometry &g);
+// Whether launch_search takes the one-workgroup search with shape t (null: the rule).
+bool small_search_used(const Geometry &g, const LaunchTune *t);
 // t: the launch shape (rows and lanes per stream per level, coarse levels), or null for the rules.
 hipError_t launch_search(SearchArgs a, int device_cus, hipStream_t s, const LaunchTune *t = nullptr);
 

@@ -1531,6 +1531,292 @@ __global__ __launch_bounds__(256) void k_search_fine(SearchArgs a)
     level_finish(a, pair, acc);
 }
 
+// ---------------------------------------------------------------- one-workgroup search
+
+// A pair whose bitmap pyramids fit LDS is searched by one workgroup of
+// kSmallThreads lanes: both images' planes are copied into LDS once, then
+// every level's nine candidates are scored there, the chosen shift feeding
+// the next level without leaving the workgroup.
+constexpr int kSmallThreads = 1024;
+
+// The three words of moving row j around a column word's shifted window
+// (words q .. q+2, q = k + floor((-bx - 1) / 32)) turned into the copies for
+// ddx = -1, 0, +1 (shift3c; r = (-bx - 1) mod 32 fixes kCase).  Words outside
+// the row, and rows outside the level, count with their exclusion bits
+// cleared; their indices are clamped so that every read stays in the plane.
+template <int kCase>
+__device__ __forceinline__ void small_moving(const uint32_t *mT, const uint32_t *mE, int h, int n32, int j, int q,
+                                             uint32_t r, uint32_t *st, uint32_t *se)
+{
+    const uint32_t rm = (uint32_t)j < (uint32_t)h ? ~0u : 0u;
+    const int jc = j < 0 ? 0 : (j >= h ? h - 1 : j);
+    uint32_t wt[3], we[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int w = q + i;
+        const uint32_t cm = (w >= 0 && w < n32) ? rm : 0u;
+        const int wc = w < 0 ? 0 : (w >= n32 ? n32 - 1 : w);
+        wt[i] = mT[jc * n32 + wc];
+        we[i] = mE[jc * n32 + wc] & cm;
+    }
+    shift3c<kCase>(wt, r, st);
+    shift3c<kCase>(we, r, se);
+}
+
+// Adds the three ddx candidates of one ddy for a reference word pair (rt, re).
+__device__ __forceinline__ void small_score3(uint32_t rt, uint32_t re, const uint32_t *st, const uint32_t *se,
+                                             uint32_t *acc)
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        acc[d] += __builtin_popcount((rt ^ st[d]) & re & se[d]);
+}
+
+// Nine candidate errors of one level from LDS planes of h rows of n32 words
+// (rT, rE: reference; mT, mE: moving) around the centre (bx, by), by the
+// whole workgroup.  Work item (k, s) is column word k and the rows
+// [s R, s R + R) of row stream s, walked top to bottom: reference row y meets
+// moving rows y - by - ddy for ddy = +1, 0, -1, which are carried from one
+// row to the next, so that each step loads one moving row.
+template <int kCase>
+__device__ void small_level(const uint32_t *rT, const uint32_t *rE, const uint32_t *mT, const uint32_t *mE,
+                            int h, int n32, int bx, int by, uint32_t *acc)
+{
+    int S = n32 >= kSmallThreads ? 1 : kSmallThreads / n32;
+    S = S < h ? S : h;
+    const int R = (h + S - 1) / S;
+    const int u = -bx - 1;
+    const uint32_t r = (uint32_t)u & 31u;
+    for (int item = threadIdx.x; item < n32 * S; item += kSmallThreads) {
+        const int k = item % n32, s = item / n32;
+        const int y0 = s * R, y1 = y0 + R < h ? y0 + R : h;
+        const int q = k + (u >> 5);  // arithmetic shift: floor((-bx - 1) / 32)
+        uint32_t at[3], ae[3], bt[3], be[3];
+        small_moving<kCase>(mT, mE, h, n32, y0 - by - 1, q, r, at, ae);  // ddy = +1 for row y0
+        small_moving<kCase>(mT, mE, h, n32, y0 - by, q, r, bt, be);      // ddy = 0
+        for (int y = y0; y < y1; ++y) {
+            uint32_t ct[3], ce[3];
+            small_moving<kCase>(mT, mE, h, n32, y - by + 1, q, r, ct, ce);  // ddy = -1
+            const uint32_t rt = rT[y * n32 + k], re = rE[y * n32 + k];
+            small_score3(rt, re, ct, ce, acc);
+            small_score3(rt, re, bt, be, acc + 3);
+            small_score3(rt, re, at, ae, acc + 6);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                at[d] = bt[d];
+                ae[d] = be[d];
+                bt[d] = ct[d];
+                be[d] = ce[d];
+            }
+        }
+    }
+}
+
+// The same for a level of at most kSmallThreads (row, column word)
+// positions: thread i takes position i (row-major), with its three moving
+// rows loaded afresh.
+template <int kCase>
+__device__ void small_level_pos(const uint32_t *rT, const uint32_t *rE, const uint32_t *mT, const uint32_t *mE,
+                                int h, int n32, int bx, int by, uint32_t *acc)
+{
+    const int pos = threadIdx.x;
+    if (pos >= h * n32)
+        return;
+    const int u = -bx - 1;
+    const uint32_t r = (uint32_t)u & 31u;
+    const int y = pos / n32, k = pos - y * n32;
+    const int q = k + (u >> 5);
+    const uint32_t rt = rT[pos], re = rE[pos];
+    uint32_t st[3], se[3], mt[3], me[3], nt[3], ne[3];
+    small_moving<kCase>(mT, mE, h, n32, y - by + 1, q, r, st, se);  // ddy = -1
+    small_moving<kCase>(mT, mE, h, n32, y - by, q, r, mt, me);      // ddy = 0
+    small_moving<kCase>(mT, mE, h, n32, y - by - 1, q, r, nt, ne);  // ddy = +1
+    small_score3(rt, re, st, se, acc);
+    small_score3(rt, re, mt, me, acc + 3);
+    small_score3(rt, re, nt, ne, acc + 6);
+}
+
+// Wave-uniform totals t[i] of v[i] over the wavefront: within each row of 16
+// lanes DPP moves give every lane its row's sum (as in wave_sums), then the
+// four rows' sums are read from lanes 0, 16, 32 and 48.
+template <int N>
+__device__ __forceinline__ void wave_totals(uint32_t *v, uint32_t *t)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)  // quad_perm [1,0,3,2]
+        v[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[i], 0xb1, 0xf, 0xf, true);
+#pragma unroll
+    for (int i = 0; i < N; ++i)  // quad_perm [2,3,0,1]
+        v[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[i], 0x4e, 0xf, 0xf, true);
+#pragma unroll
+    for (int i = 0; i < N; ++i)  // row_half_mirror
+        v[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[i], 0x141, 0xf, 0xf, true);
+#pragma unroll
+    for (int i = 0; i < N; ++i)  // row_mirror
+        v[i] += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[i], 0x140, 0xf, 0xf, true);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        t[i] = (uint32_t)__builtin_amdgcn_readlane((int)v[i], 0) + (uint32_t)__builtin_amdgcn_readlane((int)v[i], 16) +
+               (uint32_t)__builtin_amdgcn_readlane((int)v[i], 32) + (uint32_t)__builtin_amdgcn_readlane((int)v[i], 48);
+}
+
+// Where one pair's results go (SearchOutputs resolved for its output row),
+// read from the kernel arguments once at the start.
+struct SmallOut {
+    uint32_t *trace;      // null, or this row's L x 9 errors
+    int32_t *lvs;         // null, or this row's L x 2 shifts
+    int32_t *shift;       // this row's shift
+    uint32_t *err;        // this row's error
+};
+
+// The level's shift from its nine (wave-uniform) totals, recorded by thread
+// 0; (bx, by) moves to the next level's centre.
+__device__ __forceinline__ void small_choose(const SmallOut &o, int l, const uint32_t *c, int &bx, int &by)
+{
+    const int best = argmin9(c);
+    const int sx = bx + best % 3 - 1, sy = by + best / 3 - 1;
+    if (threadIdx.x == 0) {
+        if (o.trace)
+            for (int i = 0; i < 9; ++i)
+                o.trace[l * 9 + i] = c[i];
+        if (o.lvs) {
+            o.lvs[2 * l] = sx;
+            o.lvs[2 * l + 1] = sy;
+        }
+        if (l == 0) {
+            o.shift[0] = sx;
+            o.shift[1] = sy;
+            o.err[0] = c[best];
+        }
+    }
+    bx = 2 * sx;
+    by = 2 * sy;
+}
+
+// Level l by the whole workgroup.  Each wave adds its totals into tot[l % 3]
+// with LDS atomics; after one barrier every lane reads the sums.  Thread 0
+// clears the next level's buffer tot[(l - 1) % 3] before this barrier: its
+// last readers (two levels up) read it before arriving at the previous
+// level's barrier, which thread 0 has passed.
+__device__ __forceinline__ void small_level_all(const SmallOut &o, int l, int4 lv, const uint32_t *ref,
+                                                const uint32_t *mov, uint32_t (*tot)[9], int &bx, int &by)
+{
+    const int h = lv.x, n32 = lv.y, to = lv.z, eo = lv.w;
+    uint32_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t r = (uint32_t)(-bx - 1) & 31u;
+    const uint32_t *rT = ref + to, *rE = ref + eo, *mT = mov + to, *mE = mov + eo;
+    if (h * n32 <= kSmallThreads) {
+        if (r <= 29)
+            small_level_pos<0>(rT, rE, mT, mE, h, n32, bx, by, acc);
+        else if (r == 30)
+            small_level_pos<1>(rT, rE, mT, mE, h, n32, bx, by, acc);
+        else
+            small_level_pos<2>(rT, rE, mT, mE, h, n32, bx, by, acc);
+    } else {
+        if (r <= 29)
+            small_level<0>(rT, rE, mT, mE, h, n32, bx, by, acc);
+        else if (r == 30)
+            small_level<1>(rT, rE, mT, mE, h, n32, bx, by, acc);
+        else
+            small_level<2>(rT, rE, mT, mE, h, n32, bx, by, acc);
+    }
+    uint32_t t[9];
+    wave_totals<9>(acc, t);
+    uint32_t *tb = tot[l % 3];
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            if (t[i])
+                atomicAdd(&tb[i], t[i]);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            tot[(l + 2) % 3][i] = 0u;
+    __syncthreads();
+    uint32_t c[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        c[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)tb[i]);
+    small_choose(o, l, c, bx, by);
+}
+
+// Grid: one workgroup per pair.  The bitmaps buffer of an image holds its
+// planes between the leading guard and the medians, span = med_off - kAlign
+// bytes; the reference's span goes to LDS offset 0, the moving image's after
+// it, so that a plane's LDS offset is its buffer offset less kAlign.
+constexpr int kSmallSpan16 = (int)(kSmallLdsBytes / 32);  // uint4 of one image's span, at most
+constexpr int kStage = (kSmallSpan16 + kSmallThreads - 1) / kSmallThreads;
+
+// A lane's share of one image's span, in named registers (loads of clang
+// vector types stay in registers, where HIP's uint4 copies through memcpy and
+// an array of them can land in scratch memory): elements f, f + kSmallThreads,
+// ...; indices past the span are clamped to its last element, which is then
+// stored several times over with the same value, so that no load sits behind
+// a branch and every lane's loads are in flight together.
+struct SmallStage {
+    static_assert(kStage == 5, "five elements per lane");
+    U32x4 v0, v1, v2, v3, v4;
+    __device__ __forceinline__ static int at(int f, int j, int n16)
+    {
+        return f + j * kSmallThreads < n16 ? f + j * kSmallThreads : n16 - 1;
+    }
+    __device__ __forceinline__ void load(const U32x4 *src, int f, int n16)
+    {
+        v0 = src[at(f, 0, n16)];
+        v1 = src[at(f, 1, n16)];
+        v2 = src[at(f, 2, n16)];
+        v3 = src[at(f, 3, n16)];
+        v4 = src[at(f, 4, n16)];
+    }
+    __device__ __forceinline__ void store(U32x4 *dst, int f, int n16) const
+    {
+        dst[at(f, 0, n16)] = v0;
+        dst[at(f, 1, n16)] = v1;
+        dst[at(f, 2, n16)] = v2;
+        dst[at(f, 3, n16)] = v3;
+        dst[at(f, 4, n16)] = v4;
+    }
+};
+
+__global__ __launch_bounds__(kSmallThreads) void k_search_small(SearchArgs a)
+{
+    __shared__ U32x4 planes[kSmallLdsBytes / 16];
+    __shared__ uint32_t tot[3][9];
+    __shared__ int4 s_lv[kMaxLevels];  // per level: rows, words per row, T and E plane offsets (words)
+    __shared__ SmallOut s_out;
+    const Geometry &g = a.g;
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x;
+    // Each level's geometry and the output addresses are read from the kernel
+    // arguments once, while the planes load, and kept in LDS: the level loop
+    // then makes no dependent argument load.
+    const LevelGeom glv = g.lv[tid < g.L ? tid : 0];
+    if (tid == 0) {
+        const SearchOutputs &o = a.out;
+        const int64_t r = o.pair_image[p];
+        s_out.trace = o.trace ? o.trace + r * g.L * 9 : nullptr;
+        s_out.lvs = o.level_shifts ? o.level_shifts + r * g.L * 2 : nullptr;
+        s_out.shift = o.shifts + 2 * r;
+        s_out.err = o.errs + r;
+    }
+    const int n16 = (int)((g.med_off - kAlign) / 16);
+    SmallStage x, y;
+    x.load((const U32x4 *)(a.ref[p] + kAlign), tid, n16);
+    y.load((const U32x4 *)(a.mov[p] + kAlign), tid, n16);
+    if (tid < g.L)
+        s_lv[tid] = make_int4(glv.h, 2 * glv.wpr, (int)((glv.tb_off - kAlign) / 4), (int)((glv.eb_off - kAlign) / 4));
+    if (tid < 27)
+        (&tot[0][0])[tid] = 0u;
+    x.store(planes, tid, n16);
+    y.store(planes + n16, tid, n16);
+    __syncthreads();
+    const uint32_t *ref = (const uint32_t *)planes, *mov = ref + 4 * n16;
+    const SmallOut o = s_out;
+    int bx = 0, by = 0;
+    for (int l = g.L - 1; l >= 0; --l)
+        small_level_all(o, l, s_lv[l], ref, mov, tot, bx, by);
+}
+
 // Byte-map search (comparison path): each lane owns one dword (four pixels) of
 // a reference row; a wavefront covers 64 dwords x `rows` rows.  The three
 // horizontal shifts of a moving dword come from v_alignbyte over three
@@ -1943,9 +2229,18 @@ int coarse_levels_used(const Geometry &g, int npairs, const LaunchTune *t)
     return t->coarse < most ? t->coarse : most;
 }
 
+bool small_search_fits(const Geometry &g) { return 2 * (g.med_off - kAlign) <= kSmallLdsBytes; }
+
+bool small_search_used(const Geometry &g, const LaunchTune *t)
+{
+    return (!t || t->small != 0) && small_search_fits(g);
+}
+
 hipError_t launch_search(SearchArgs a, int cus, hipStream_t s, const LaunchTune *t)
 {
     const Geometry &g = a.g;
+    if (small_search_used(g, t))
+        return launch_kernel("k_search_small", k_search_small, dim3(a.npairs), dim3(kSmallThreads), s, a);
     const int cn = coarse_levels_used(g, a.npairs, t);
     a.coarse_n = cn;
     hipError_t e = hipSuccess;

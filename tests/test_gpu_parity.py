@@ -307,10 +307,10 @@ def test_full_size_stack_7x6000x4000(mtb):
     _check_stack(mtb, imgs, w.levels, ref_index=ref)
 
 
-def test_small_pair_searches_every_level_in_one_launch(mtb):
-    # A 512x384 pair's five levels fit the exhaustive windows' work budget
-    # (radius 1 .. 31 from the coarsest down): the search is one zeroing and
-    # one coarse launch, and every level's nine errors still equal the oracle's.
+def test_small_pair_search_is_one_launch(mtb):
+    # A 512x384 pair's two bitmap pyramids fit one workgroup's LDS: the
+    # search is a single launch with no zeroed state, and every level's nine
+    # errors still equal the oracle's.
     (imgs, _, _), = synth.workload("pair_512x384").stacks
     ref, mov = imgs
     h, w, _ = ref.shape
@@ -321,5 +321,29 @@ def test_small_pair_searches_every_level_in_one_launch(mtb):
     mtb.mtb_align_pair(br, bmv, w, h, 5)
     torch.cuda.synchronize()
     launches = {k: c for k, (c, _) in mtb.mtb_profile_end().items()}
-    assert launches == {"k_zero": 1, "k_search_coarse": 1}, launches
+    assert launches == {"k_search_small": 1}, launches
     _check_pair(mtb, ref, mov, 5)
+
+
+# Sizes on both sides of the one-workgroup search's LDS limit (144 KiB for
+# both pyramids' planes), odd widths and heights, one-row and one-column
+# images, and the most levels the size allows.
+@pytest.mark.parametrize("w,h,L", [(512, 384, 5), (530, 380, 6), (600, 420, 4), (129, 97, 7), (1000, 100, 3),
+                                   (2000, 40, 6), (37, 600, 5), (1, 500, 1), (700, 1, 1), (64, 64, 7)])
+def test_one_workgroup_search_equals_launch_chain(mtb, w, h, L):
+    # Stacks of three: the one-workgroup search (the rule, where it fits) and
+    # the coarse and fine launches (small_search 0) give identical shifts,
+    # errors and traces, equal to the oracle's.
+    imgs, _, _ = synth.make_stack(w, h, 3, 12, 900 + w + h, min(w, h) // 4, sat_frac=0.05)
+    d = [_to_dev(im) for im in imgs]
+    mtb.mtb_tune_reset()
+    got = mtb.mtb_align_stack(d, L, trace=True)
+    mtb.mtb_set_shape(3, w, h, 3 * w, L, {"small_search": 0})
+    alt = mtb.mtb_align_stack(d, L, trace=True)
+    torch.cuda.synchronize()
+    mtb.mtb_tune_reset()
+    for k in ("shifts", "errs", "trace"):
+        assert np.array_equal(got[k].cpu().numpy(), alt[k].cpu().numpy()), k
+    want = oracle.align_stack(imgs, L, threads=4, keep=False)
+    assert np.array_equal(got["shifts"].cpu().numpy(), want["shifts"])
+    assert np.array_equal(got["errs"].cpu().numpy().astype(np.int64), want["errs"])

@@ -59,7 +59,7 @@ def test_tuned_shape_keeps_results_and_is_stored(mtb):
     stored = mtb.mtb_tuned_shape(5, 900, 640, 2700, L)
     assert stored is not None
     keys = ("pyramid_slots_pct", "pyramid_tile_group", "bitmaps_blocks_pct", "bitmaps_waves", "coarse_levels",
-            "search_rows", "search_lanes")
+            "small_search", "search_rows", "search_lanes")
     assert {k: stored[k] for k in keys} == {k: shape[k] for k in keys}
     after = _run(mtb, d, L)
     for a, b in zip(before, after):
@@ -99,7 +99,7 @@ def test_tuned_shapes_survive_save_and_load(mtb, tmp_path):
     path = str(tmp_path / "shapes.txt")
     mtb.mtb_tune_save(path)
     first = open(path).readline().split()
-    assert first[:2] == ["mtb-tune", "1"] and first[2].startswith("gfx950") and first[3].startswith("hip-")
+    assert first[:2] == ["mtb-tune", "2"] and first[2].startswith("gfx950") and first[3].startswith("hip-")
     mtb.mtb_tune_reset()
     assert mtb.mtb_tuned_shape(4, 1100, 700, 3300, 6) is None
     assert mtb.mtb_tune_load(path) == 1
@@ -107,7 +107,7 @@ def test_tuned_shapes_survive_save_and_load(mtb, tmp_path):
     # A file written on another platform is skipped whole.
     other = str(tmp_path / "other.txt")
     lines = open(path).read().splitlines()
-    open(other, "w").write("\n".join(["mtb-tune 1 gfx942 hip-1"] + lines[1:]) + "\n")
+    open(other, "w").write("\n".join(["mtb-tune 2 gfx942 hip-1"] + lines[1:]) + "\n")
     mtb.mtb_tune_reset()
     assert mtb.mtb_tune_load(other) == 0
     assert mtb.mtb_tuned_shape(4, 1100, 700, 3300, 6) is None
