@@ -85,7 +85,7 @@ def load_traffic(workload):
     """HBM bytes per launch of every kernel of one step, from the committed
     rocprofv3 counter runs, if they were taken on this workload and the kernel
     sources are unchanged since; {} otherwise.  Keys are kernel names (search
-    launches carry their level: "k_search_fine@l0", ...)."""
+    launches of one kernel at several grid sizes carry the grid: "k_search_fine[196608]", ...)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
