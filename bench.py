@@ -211,9 +211,11 @@ def pyramid_bytes(W, H, L):
     return 3 * W * H + sum((W >> l) * (H >> l) for l in range(L))
 
 
-def run_batch(args, mtb, synth, torch, np, dev):
+def run_batch(args, mtb, synth, torch, np, dev, compact=False):
     """64 pairs of uneven sizes: the batched call, its HIP-graph replay, and the plain
-    per-pair launch sequence (two pyramids, two bitmap passes, one pair search per item)."""
+    per-pair launch sequence (two pyramids, two bitmap passes, one pair search per item).
+    Returns the bench line; compact (a summary inside another workload's line):
+    only the batched and plain timings, no tuning, graph or CPU leg."""
     log("generating batch64_uneven ...")
     t0 = time.perf_counter()
     batch = synth.make_batch(64, 4)
@@ -262,7 +264,7 @@ def run_batch(args, mtb, synth, torch, np, dev):
         return (time.perf_counter() - t) * 1e3 / steps
 
     tuned_keys = None
-    if args.tune:
+    if args.tune and not compact:
         # The library's tuner picks every group key's shape once, before timing.
         tuned_keys = mtb.mtb_tune_batch(pairs, workspace=ws, shifts=shifts, errs=errs)
         log(f"tuned {tuned_keys} group shapes")
@@ -283,6 +285,12 @@ def run_batch(args, mtb, synth, torch, np, dev):
 
     ms_plain = timed(per_pair, max(1, args.steps // 4), 1)
     same = bool(torch.equal(pshift, shifts) and torch.equal(perr, errs))
+    if compact:
+        return {"workload": "batch64_uneven", "pairs": n, "megapixels_per_step": round(mp_total, 3),
+                "ms_per_step": round(ms_batched, 4), "MPps": round(mp_total / (ms_batched / 1e3), 1),
+                "plain_per_pair": {"ms_per_step": round(ms_plain, 4), "MPps": round(mp_total / (ms_plain / 1e3), 1),
+                                   "same_results": same},
+                "batched_vs_plain": round(ms_plain / ms_batched, 3)}
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -344,7 +352,7 @@ def run_batch(args, mtb, synth, torch, np, dev):
                                             f"pairs spread over {threads} threads"}
         result["parity_vs_oracle"] = bool(
             all(tuple(got_s[k]) == w["shift"] and got_e[k] == w["err"] for k, w in enumerate(want)))
-    print(json.dumps(result), flush=True)
+    return result
 
 
 def run_apply(args, mtb, synth, torch, np, dev):
@@ -501,13 +509,16 @@ def tune_served_buckets(mtb, synth, base_dev, BW, BH):
     return count
 
 
-def run_served(args, mtb, synth, torch, np, dev):
+def run_served(args, mtb, synth, torch, np, dev, compact_seconds=0.0):
     """Poisson arrivals of exposure stacks served with continuous batching.
 
     Device-staged: the requests are crops of a base scene resident on the GPU.
     Host-staged: the same crops are cut from a copy of the base in pinned host
     memory and copied to the device (mtb_stage_rgb) inside each request, so
-    their latency includes the host-to-device transfer."""
+    their latency includes the host-to-device transfer.  Returns the bench
+    line; with compact_seconds (a summary inside another workload's line)
+    only that long a device-staged run at 200/s, through the stack path and
+    the plain per-call path, no tuning, sweeps, host staging or CPU leg."""
     from paper_2007_06483_amd.serving import Request, Server, footprint_bytes, gpu_executor, percentile
 
     BW, BH = 8704, 5888
@@ -515,7 +526,8 @@ def run_served(args, mtb, synth, torch, np, dev):
     t0 = time.perf_counter()
     base = synth.make_serve_base(BW, BH, 5)
     base_dev = [torch.from_numpy(b).to(dev) for b in base]
-    base_host = [torch.from_numpy(b).pin_memory() for b in base] if args.serve_host_seconds > 0 else None
+    base_host = ([torch.from_numpy(b).pin_memory() for b in base]
+                 if args.serve_host_seconds > 0 and not compact_seconds else None)
     log(f"generated in {time.perf_counter() - t0:.1f} s")
 
     def requests(seed, rate, seconds, host, plain=False):
@@ -537,7 +549,7 @@ def run_served(args, mtb, synth, torch, np, dev):
     execute_plain, poll_plain = gpu_executor(pool, slots, plain=True)
 
     tuned = None
-    if args.tune:
+    if args.tune and not compact_seconds:
         tuned = tune_served_buckets(mtb, synth, base_dev, BW, BH)
         log(f"tuned {tuned} size-bucket shapes")
         save_tune_cache(args, mtb)
@@ -567,6 +579,16 @@ def run_served(args, mtb, synth, torch, np, dev):
         return out
 
     serve(200.0, 0.5, 99)  # warm-up
+    if compact_seconds:
+        log(f"serving Poisson(200/s) for {compact_seconds:.0f} s, stack path then plain per-call path ...")
+        run = serve(200.0, compact_seconds, 5)
+        serve(200.0, 0.5, 99, plain=True)  # warm-up
+        plain_run = serve(200.0, compact_seconds, 5, plain=True)
+        del pool
+        torch.cuda.empty_cache()
+        return {"workload": "served_poisson200", "staging": "device (crops of a resident base)", "slots": slots,
+                "latency_ms": {"p50": run["p50_ms"], "p99": run["p99_ms"]}, "served": run,
+                "plain_per_call": plain_run}
     log(f"serving Poisson(200/s) for {args.serve_seconds:.0f} s ...")
     main_run = serve(200.0, args.serve_seconds, 5, keep=True)
     log(json.dumps(main_run))
@@ -651,7 +673,7 @@ def run_served(args, mtb, synth, torch, np, dev):
     if cpu is not None:
         result["cpu_baseline"] = {k: v for k, v in cpu.items() if k != "parity_vs_gpu"}
         result["parity_vs_oracle"] = cpu["parity_vs_gpu"]
-    print(json.dumps(result), flush=True)
+    return result
 
 
 def main():
@@ -685,6 +707,10 @@ def main():
                     help="minimum wall time of the CPU oracle sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--forms-seconds", type=float, default=5.0,
+                    help="default stack workload: also serve Poisson(200/s) for this many seconds through the "
+                         "stack path and the plain per-call path, and time the 64-pair uneven batch against "
+                         "its plain per-pair sequence; both summaries go into the line under 'forms' (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -710,9 +736,11 @@ def main():
         log(f"launch shapes loaded from {args.tune_cache}: {mtb.mtb_tune_load(args.tune_cache)}")
 
     if args.workload == "batch64_uneven":
-        return run_batch(args, mtb, synth, torch, np, dev)
+        print(json.dumps(run_batch(args, mtb, synth, torch, np, dev)), flush=True)
+        return None
     if args.workload == "served_poisson200":
-        return run_served(args, mtb, synth, torch, np, dev)
+        print(json.dumps(run_served(args, mtb, synth, torch, np, dev)), flush=True)
+        return None
     if args.workload == "apply7_6000x4000":
         return run_apply(args, mtb, synth, torch, np, dev)
     if args.workload == "quadrants7_6000x4000":
@@ -908,6 +936,12 @@ def main():
                                           np.array_equal(gpu_errs, want["errs"]))
     result["shifts"] = gpu_shifts.tolist()
     result["planted_translations"] = [list(t) for t in true_shifts]
+    if args.workload == "stack7_6000x4000" and args.forms_seconds > 0:
+        # The served and batched forms of the same path, so that the default
+        # line carries their latency and their gain over the plain per-call
+        # launches (their own workloads report them in full).
+        result["forms"] = {"served": run_served(args, mtb, synth, torch, np, dev, compact_seconds=args.forms_seconds),
+                           "batch": run_batch(args, mtb, synth, torch, np, dev, compact=True)}
     print(json.dumps(result), flush=True)
 
 
