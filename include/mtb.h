@@ -457,6 +457,43 @@ mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32
                            void *d_workspace, size_t workspace_bytes, int32_t *d_shifts,
                            uint32_t *d_errs, void *stream);
 
+/* One exposure stack of a stacked batch (see mtb_align_batch_stacks). */
+typedef struct mtb_batch_stack {
+    const uint8_t *const *d_rgb; /* host array of n device RGB images, one size and row stride */
+    int32_t n;                   /* images, 1 .. MTB_MAX_STACK */
+    int32_t ref_index;           /* reference image, -1 for n / 2 */
+    int64_t row_stride;
+    int32_t width, height;
+    int32_t levels;
+    int32_t reserved;            /* must be 0 */
+} mtb_batch_stack;
+
+/* Bytes of the workspace mtb_align_batch_stacks needs; 0 if the item list
+ * or any item is invalid. */
+size_t mtb_batch_stacks_workspace_bytes(const mtb_batch_stack *h_items, int32_t n_items);
+
+/*
+ * Many exposure stacks of uneven sizes in one call: every stack aligned as
+ * mtb_align_stack aligns it (Section III-A, III-B: each image against the
+ * stack's reference, each image's pyramid and bitmaps built once).  Stacks
+ * of equal width, height, row stride and level count share launch sets, up
+ * to 32 images per launch of each pass (a stack is never split), which run
+ * on the library's stream lanes as in mtb_align_batch, with the launch shape
+ * the table holds for each set's key.  Output rows follow the items: the
+ * rows of item k start after those of items 0 .. k-1, one per image; the
+ * reference's row holds (0, 0) and error 0.  Every row is cleared on
+ * `stream` before the lanes fork.
+ *   h_items          host array of n_items stacks (1 .. MTB_MAX_BATCH)
+ *   exclude_range    as for mtb_bitmaps (Ward: 4)
+ *   d_workspace      >= mtb_batch_stacks_workspace_bytes(h_items, n_items) bytes
+ *   d_shifts         int32[rows][2], rows = the items' images together
+ *   d_errs           uint32[rows]
+ * Errors: MTB_ERR_INVALID_ARG, MTB_ERR_WORKSPACE, MTB_ERR_DEVICE.
+ */
+mtb_status mtb_align_batch_stacks(const mtb_batch_stack *h_items, int32_t n_items, int32_t exclude_range,
+                                  void *d_workspace, size_t workspace_bytes, int32_t *d_shifts,
+                                  uint32_t *d_errs, void *stream);
+
 /*
  * Tunes the launch shapes of a batch: for each distinct group key (2 x pairs
  * of the group, width, height, levels, row-stride class; see the launch

@@ -57,6 +57,8 @@ __all__ = [
     "MTB_FILL_EDGE",
     "mtb_batch_workspace_bytes",
     "mtb_align_batch",
+    "mtb_batch_stacks_workspace_bytes",
+    "mtb_align_batch_stacks",
     "mtb_profile_begin",
     "mtb_profile_end",
     "mtb_profile_pause",
@@ -103,6 +105,12 @@ class _CLayout(ctypes.Structure):
         ("median_offset", ctypes.c_int64),
         ("bitmaps_bytes", ctypes.c_int64),
     ]
+
+
+class _BatchStack(ctypes.Structure):
+    _fields_ = [("d_rgb", ctypes.POINTER(ctypes.c_void_p)), ("n", ctypes.c_int32), ("ref_index", ctypes.c_int32),
+                ("row_stride", ctypes.c_int64), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _BatchItem(ctypes.Structure):
@@ -237,6 +245,10 @@ def lib():
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
     L.mtb_batch_workspace_bytes.restype = sz
     L.mtb_align_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P]
+    L.mtb_batch_stacks_workspace_bytes.argtypes = [ctypes.POINTER(_BatchStack), i32]
+    L.mtb_batch_stacks_workspace_bytes.restype = sz
+    L.mtb_align_batch_stacks.argtypes = [ctypes.POINTER(_BatchStack), i32, i32, P, sz, P, P, P]
+    L.mtb_align_batch_stacks.restype = ctypes.c_int
     L.mtb_probe_stream.argtypes = [P, sz, P, sz, P]
     L.mtb_probe_stream.restype = ctypes.c_int
     L.mtb_tune_batch.argtypes = [ctypes.POINTER(_BatchItem), i32, i32, P, sz, P, P, P, ctypes.POINTER(i32)]
@@ -635,6 +647,58 @@ def mtb_align_batch(pairs, exclude_range: int = 4, workspace: torch.Tensor | Non
            lib().mtb_align_batch(items, n, exclude_range, _ptr(workspace), workspace.numel(),
                                  _ptr(shifts), _ptr(errs), _stream(stream)))
     return {"shifts": shifts, "errs": errs, "workspace": workspace}
+
+
+def _batch_stacks(stacks):
+    """[(images, levels[, ref_index]), ...] -> (ctypes item array, pointer arrays to keep alive,
+    first output row of each stack, rows)."""
+    n = len(stacks)
+    if not 1 <= n <= MTB_MAX_BATCH:
+        raise ValueError(f"a batch holds 1..{MTB_MAX_BATCH} items")
+    items = (_BatchStack * n)()
+    keep, starts, rows = [], [], 0
+    for i, st in enumerate(stacks):
+        images, levels = st[0], st[1]
+        ref = -1 if len(st) < 3 or st[2] is None else int(st[2])
+        if not 1 <= len(images) <= MTB_MAX_STACK:
+            raise ValueError(f"a stack holds 1..{MTB_MAX_STACK} images")
+        geo = _rgb_geometry(images[0])
+        for im in images[1:]:
+            if _rgb_geometry(im) != geo or im.device != images[0].device:
+                raise ValueError("the images of a stack must share size, stride and device")
+        W, H, stride = geo
+        ptrs = (ctypes.c_void_p * len(images))(*[im.data_ptr() for im in images])
+        keep.append(ptrs)
+        items[i] = _BatchStack(ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), len(images), ref, stride, W, H,
+                               int(levels), 0)
+        starts.append(rows)
+        rows += len(images)
+    return items, keep, starts, rows
+
+
+def mtb_batch_stacks_workspace_bytes(stacks) -> int:
+    """Workspace bytes for mtb_align_batch_stacks over [(images, levels[, ref_index]), ...]."""
+    items, _keep, _, _ = _batch_stacks(stacks)
+    return int(lib().mtb_batch_stacks_workspace_bytes(items, len(stacks)))
+
+
+def mtb_align_batch_stacks(stacks, exclude_range: int = 4, workspace: torch.Tensor | None = None,
+                           shifts=None, errs=None, stream=None) -> dict:
+    """Align every exposure stack (images, levels[, ref_index]) of a batch; sizes may differ
+    between stacks.  Returns device tensors ``shifts`` int32[rows][2] and ``errs`` int32[rows]
+    (one row per image, stacks one after another) and ``starts``, each stack's first row."""
+    items, _keep, starts, rows = _batch_stacks(stacks)
+    dev = stacks[0][0][0].device
+    need = int(lib().mtb_batch_stacks_workspace_bytes(items, len(stacks)))
+    workspace = _buffer(max(need, 1), dev, workspace)
+    if shifts is None:
+        shifts = torch.empty((rows, 2), dtype=torch.int32, device=dev)
+    if errs is None:
+        errs = torch.empty(rows, dtype=torch.int32, device=dev)
+    _check("mtb_align_batch_stacks",
+           lib().mtb_align_batch_stacks(items, len(stacks), exclude_range, _ptr(workspace), workspace.numel(),
+                                        _ptr(shifts), _ptr(errs), _stream(stream)))
+    return {"shifts": shifts, "errs": errs, "starts": starts, "workspace": workspace}
 
 
 def mtb_tune_batch(pairs, exclude_range: int = 4, workspace: torch.Tensor | None = None,

@@ -461,47 +461,132 @@ mtb_status tune_one(const Geometry &g, int npairs, int cus, hipStream_t s, Run r
     return MTB_OK;
 }
 
-// Items of a batch that share one launch set: same geometry and stride, at
-// most kMaxStack / 2 pairs.
-struct BatchGroup {
-    int first;  // an item of the group, for its geometry and stride
-    std::vector<int> items;
+// One unit of a batch: the images of a pair item or a stack item (one size
+// and row stride), its reference and its output rows.  A pair item (images
+// reference, moving) writes one row, row0; a stack item writes row row0 + i
+// for image i, zeros for its reference.
+struct BatchUnit {
+    const uint8_t *img[kMaxStack];
+    int n = 0, ref = 0;
+    int32_t W = 0, H = 0, L = 0;
+    int64_t stride = 0;
+    int row0 = 0;
+    bool is_pair = false;
 };
-
-// Splits a valid item list into launch sets, in order of first appearance.
-std::vector<BatchGroup> batch_groups(const mtb_batch_item *it, int n)
-{
-    std::vector<BatchGroup> groups;
-    std::vector<int> open;  // index into groups of the last group of each size seen
-    for (int i = 0; i < n; ++i) {
-        int found = -1;
-        for (int k : open) {
-            const mtb_batch_item &f = it[groups[k].first];
-            if (f.width == it[i].width && f.height == it[i].height && f.levels == it[i].levels &&
-                f.row_stride == it[i].row_stride) {
-                found = k;
-                break;
-            }
-        }
-        if (found >= 0 && (int)groups[found].items.size() == kMaxStack / 2) {
-            for (int &k : open)
-                if (k == found)
-                    k = (int)groups.size();
-            groups.push_back(BatchGroup{i, {i}});
-        } else if (found >= 0) {
-            groups[found].items.push_back(i);
-        } else {
-            open.push_back((int)groups.size());
-            groups.push_back(BatchGroup{i, {i}});
-        }
-    }
-    return groups;
-}
 
 bool batch_item_valid(const mtb_batch_item &it, Geometry *g)
 {
     return it.d_ref_rgb && it.d_mov_rgb && it.reserved == 0 && make_geometry(it.width, it.height, it.levels, g) &&
            it.row_stride >= 3 * (int64_t)it.width;
+}
+
+bool batch_stack_valid(const mtb_batch_stack &st, Geometry *g)
+{
+    if (!st.d_rgb || st.n < 1 || st.n > kMaxStack || st.ref_index < -1 || st.ref_index >= st.n || st.reserved != 0 ||
+        st.row_stride < 3 * (int64_t)st.width || !make_geometry(st.width, st.height, st.levels, g))
+        return false;
+    for (int i = 0; i < st.n; ++i)
+        if (!st.d_rgb[i])
+            return false;
+    return true;
+}
+
+// Units of valid pair items (item k writes row k), or of valid stack items
+// (rows in item order, image by image); false if any item is invalid.
+bool pair_units(const mtb_batch_item *it, int n, std::vector<BatchUnit> *u)
+{
+    u->assign(n, BatchUnit());
+    Geometry g;
+    for (int i = 0; i < n; ++i) {
+        if (!batch_item_valid(it[i], &g))
+            return false;
+        BatchUnit &b = (*u)[i];
+        b.img[0] = it[i].d_ref_rgb;
+        b.img[1] = it[i].d_mov_rgb;
+        b.n = 2;
+        b.ref = 0;
+        b.W = it[i].width;
+        b.H = it[i].height;
+        b.L = it[i].levels;
+        b.stride = it[i].row_stride;
+        b.row0 = i;
+        b.is_pair = true;
+    }
+    return true;
+}
+
+bool stack_units(const mtb_batch_stack *st, int n, std::vector<BatchUnit> *u, int64_t *rows)
+{
+    u->assign(n, BatchUnit());
+    Geometry g;
+    int64_t row = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!batch_stack_valid(st[i], &g))
+            return false;
+        BatchUnit &b = (*u)[i];
+        for (int k = 0; k < st[i].n; ++k)
+            b.img[k] = st[i].d_rgb[k];
+        b.n = st[i].n;
+        b.ref = st[i].ref_index < 0 ? st[i].n / 2 : st[i].ref_index;
+        b.W = st[i].width;
+        b.H = st[i].height;
+        b.L = st[i].levels;
+        b.stride = st[i].row_stride;
+        b.row0 = (int)row;
+        b.is_pair = false;
+        row += st[i].n;
+    }
+    *rows = row;
+    return true;
+}
+
+// Units of a batch that share one launch set: same geometry and stride, at
+// most kMaxStack images together (16 pairs).
+struct BatchGroup {
+    int first;  // a unit of the group, for its geometry and stride
+    std::vector<int> items;
+    int images = 0;
+};
+
+// Splits a unit list into launch sets, in order of first appearance; a unit
+// joins the open group of its size while the group's images stay within
+// kMaxStack, else it opens a new one.
+std::vector<BatchGroup> batch_groups(const std::vector<BatchUnit> &u)
+{
+    std::vector<BatchGroup> groups;
+    std::vector<int> open;  // index into groups of the last group of each size seen
+    for (int i = 0; i < (int)u.size(); ++i) {
+        int found = -1;
+        for (int k : open) {
+            const BatchUnit &f = u[groups[k].first];
+            if (f.W == u[i].W && f.H == u[i].H && f.L == u[i].L && f.stride == u[i].stride) {
+                found = k;
+                break;
+            }
+        }
+        if (found >= 0 && groups[found].images + u[i].n > kMaxStack) {
+            for (int &k : open)
+                if (k == found)
+                    k = (int)groups.size();
+            groups.push_back(BatchGroup{i, {i}, u[i].n});
+        } else if (found >= 0) {
+            groups[found].items.push_back(i);
+            groups[found].images += u[i].n;
+        } else {
+            open.push_back((int)groups.size());
+            groups.push_back(BatchGroup{i, {i}, u[i].n});
+        }
+    }
+    return groups;
+}
+
+// Pairs a group searches: every image of each unit but its reference.
+int group_pairs(const std::vector<BatchUnit> &u, const BatchGroup &grp)
+{
+    int np = 0;
+    for (int i : grp.items)
+        np += u[i].n - 1;
+    return np;
 }
 
 // The four quadrant pairs of a reference / moving pair as batch items
@@ -583,21 +668,20 @@ struct BatchPlan {
     int64_t lane_bytes = 0;  // workspace bytes of one lane (256-byte multiple)
 };
 
-BatchPlan batch_plan(const mtb_batch_item *h_items, int n_items)
+BatchPlan batch_plan(const std::vector<BatchUnit> &u)
 {
     BatchPlan p;
-    p.groups = batch_groups(h_items, n_items);
+    p.groups = batch_groups(u);
     const int ng = (int)p.groups.size();
     p.lanes = ng < kBatchLanes ? ng : kBatchLanes;
     std::vector<int64_t> px(ng);
     for (int k = 0; k < ng; ++k) {
-        const mtb_batch_item &f = h_items[p.groups[k].first];
+        const BatchUnit &f = u[p.groups[k].first];
         Geometry g;
-        make_geometry(f.width, f.height, f.levels, &g);
-        const int np = (int)p.groups[k].items.size();
-        const int64_t b = align_up(set_workspace_bytes(g, 2 * np, np), kAlign);
+        make_geometry(f.W, f.H, f.L, &g);
+        const int64_t b = align_up(set_workspace_bytes(g, p.groups[k].images, group_pairs(u, p.groups[k])), kAlign);
         p.lane_bytes = b > p.lane_bytes ? b : p.lane_bytes;
-        px[k] = (int64_t)f.width * f.height * np;
+        px[k] = (int64_t)f.W * f.H * p.groups[k].images;
     }
     // Largest groups first, each to the lane with the fewest pixels so far.
     std::vector<int> order(ng);
@@ -646,27 +730,38 @@ Lanes *batch_lanes()
     return &t_lanes.back();
 }
 
-// A batch: one launch set per group of items that share geometry and stride,
-// each with its key's tuned shape (or, for the key ov_key, the shape ov_shape).
-mtb_status align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range, void *d_workspace,
+// A batch: one launch set per group of units that share geometry and stride,
+// each with its key's tuned shape (or, for the key ov_key, the shape ov_shape);
+// rows output rows.  Units must be valid.
+mtb_status align_units(const std::vector<BatchUnit> &u, int64_t rows, int32_t exclude_range, void *d_workspace,
                        size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs, hipStream_t s,
                        const TuneKey *ov_key, const LaunchTune *ov_shape)
 {
-    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH || !d_workspace || !d_shifts || !d_errs)
+    if (!d_workspace || !d_shifts || !d_errs || exclude_range < 0 || exclude_range > 255)
         return MTB_ERR_INVALID_ARG;
-    if (exclude_range < 0 || exclude_range > 255)
-        return MTB_ERR_INVALID_ARG;
-    Geometry g;
-    for (int i = 0; i < n_items; ++i)
-        if (!batch_item_valid(h_items[i], &g))
-            return MTB_ERR_INVALID_ARG;
-    if (workspace_bytes < mtb_batch_workspace_bytes(h_items, n_items))
+    const BatchPlan plan = batch_plan(u);
+    if (workspace_bytes < (size_t)(plan.lanes * plan.lane_bytes + kAlign))
         return MTB_ERR_WORKSPACE;
     const int cus = current_device_cus();
     if (cus <= 0)
         return MTB_ERR_UNSUPPORTED;
     uint8_t *ws = (uint8_t *)align_up((int64_t)(uintptr_t)d_workspace, kAlign);
-    const BatchPlan plan = batch_plan(h_items, n_items);
+    // A stack item's reference rows are written by no search: clear every
+    // row first, on the caller's stream, before the lanes fork from it.
+    bool stacks = false;
+    for (const BatchUnit &b : u)
+        stacks = stacks || !b.is_pair;
+    if (stacks) {
+        ZeroArgs z;
+        memset(&z, 0, sizeof(z));
+        z.ptr[0] = (uint32_t *)d_shifts;
+        z.words[0] = 2 * rows;
+        z.ptr[1] = d_errs;
+        z.words[1] = rows;
+        z.count = 2;
+        if (launch_zero(z, s) != hipSuccess)
+            return MTB_ERR_DEVICE;
+    }
     Lanes *lanes = plan.lanes > 1 ? batch_lanes() : nullptr;
     if (plan.lanes > 1 && !lanes)
         return MTB_ERR_DEVICE;
@@ -680,36 +775,44 @@ mtb_status align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t e
     hipError_t e = hipSuccess;
     for (size_t k = 0; k < plan.groups.size() && e == hipSuccess; ++k) {
         const BatchGroup &grp = plan.groups[k];
-        const mtb_batch_item &f = h_items[grp.first];
-        make_geometry(f.width, f.height, f.levels, &g);
+        if (group_pairs(u, grp) == 0)
+            continue;  // single-image stacks only: their rows are the zeros above
+        const BatchUnit &f = u[grp.first];
+        Geometry g;
+        make_geometry(f.W, f.H, f.L, &g);
         PairSet ps;
         int align = 16;
         for (int item : grp.items) {
-            const mtb_batch_item &it = h_items[item];
-            ps.ref_img[ps.npairs] = ps.n;
-            ps.rgb[ps.n++] = it.d_ref_rgb;
-            ps.mov_img[ps.npairs] = ps.n;
-            ps.rgb[ps.n++] = it.d_mov_rgb;
-            ps.out_row[ps.npairs++] = item;
-            const int a1 = row_alignment(it.d_ref_rgb, it.row_stride), a2 = row_alignment(it.d_mov_rgb, it.row_stride);
-            align = a1 < align ? a1 : align;
-            align = a2 < align ? a2 : align;
+            const BatchUnit &b = u[item];
+            const int base = ps.n;
+            for (int i = 0; i < b.n; ++i) {
+                ps.rgb[ps.n++] = b.img[i];
+                const int a = row_alignment(b.img[i], b.stride);
+                align = a < align ? a : align;
+            }
+            for (int i = 0; i < b.n; ++i) {
+                if (i == b.ref)
+                    continue;
+                ps.ref_img[ps.npairs] = base + b.ref;
+                ps.mov_img[ps.npairs] = base + i;
+                ps.out_row[ps.npairs++] = b.is_pair ? b.row0 : b.row0 + i;
+            }
         }
         SearchOutputs out;
         memset(&out, 0, sizeof(out));
-        out.n_out = n_items;
+        out.n_out = (int32_t)rows;
         out.shifts = d_shifts;
         out.errs = d_errs;
         ZeroArgs z;
         memset(&z, 0, sizeof(z));
-        const TuneKey key = tune_key(ps.n, f.width, f.height, f.levels, f.row_stride);
+        const TuneKey key = tune_key(ps.n, f.W, f.H, f.L, f.stride);
         LaunchTune t;
         if (ov_key && *ov_key == key)
             t = *ov_shape;
         else
             tune_lookup(key, &t);
         const int l = plan.lane[k];
-        e = enqueue_set(ps, g, f.row_stride, align, exclude_range, ws + l * plan.lane_bytes, out, z, cus,
+        e = enqueue_set(ps, g, f.stride, align, exclude_range, ws + l * plan.lane_bytes, out, z, cus,
                         lanes ? lanes->s[l] : s, false, t);
     }
     // Join every lane back into the caller's stream, also after a failed
@@ -720,6 +823,18 @@ mtb_status align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t e
             joined = hipEventRecord(lanes->done[l], lanes->s[l]) == hipSuccess &&
                      hipStreamWaitEvent(s, lanes->done[l], 0) == hipSuccess && joined;
     return e == hipSuccess && joined ? MTB_OK : MTB_ERR_DEVICE;
+}
+
+// The pair-item batch.
+mtb_status align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range, void *d_workspace,
+                       size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs, hipStream_t s,
+                       const TuneKey *ov_key, const LaunchTune *ov_shape)
+{
+    std::vector<BatchUnit> u;
+    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH || !pair_units(h_items, n_items, &u))
+        return MTB_ERR_INVALID_ARG;
+    return align_units(u, n_items, exclude_range, d_workspace, workspace_bytes, d_shifts, d_errs, s, ov_key,
+                       ov_shape);
 }
 
 }  // namespace
@@ -1282,14 +1397,33 @@ mtb_status mtb_stage_rgb(const uint8_t *h_rgb, int64_t src_stride, int32_t width
 
 size_t mtb_batch_workspace_bytes(const mtb_batch_item *h_items, int32_t n_items)
 {
-    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH)
+    std::vector<BatchUnit> u;
+    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH || !pair_units(h_items, n_items, &u))
         return 0;
-    Geometry g;
-    for (int i = 0; i < n_items; ++i)
-        if (!batch_item_valid(h_items[i], &g))
-            return 0;
-    const BatchPlan plan = batch_plan(h_items, n_items);
+    const BatchPlan plan = batch_plan(u);
     return (size_t)(plan.lanes * plan.lane_bytes + kAlign);
+}
+
+size_t mtb_batch_stacks_workspace_bytes(const mtb_batch_stack *h_items, int32_t n_items)
+{
+    std::vector<BatchUnit> u;
+    int64_t rows = 0;
+    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH || !stack_units(h_items, n_items, &u, &rows))
+        return 0;
+    const BatchPlan plan = batch_plan(u);
+    return (size_t)(plan.lanes * plan.lane_bytes + kAlign);
+}
+
+mtb_status mtb_align_batch_stacks(const mtb_batch_stack *h_items, int32_t n_items, int32_t exclude_range,
+                                  void *d_workspace, size_t workspace_bytes, int32_t *d_shifts, uint32_t *d_errs,
+                                  void *stream)
+{
+    std::vector<BatchUnit> u;
+    int64_t rows = 0;
+    if (!h_items || n_items < 1 || n_items > MTB_MAX_BATCH || !stack_units(h_items, n_items, &u, &rows))
+        return MTB_ERR_INVALID_ARG;
+    return align_units(u, rows, exclude_range, d_workspace, workspace_bytes, d_shifts, d_errs, (hipStream_t)stream,
+                       nullptr, nullptr);
 }
 
 mtb_status mtb_align_batch(const mtb_batch_item *h_items, int32_t n_items, int32_t exclude_range,
@@ -1315,21 +1449,23 @@ mtb_status mtb_tune_batch(const mtb_batch_item *h_items, int32_t n_items, int32_
     // One group key after another: the whole batch is timed with candidate
     // shapes for that key, the other keys at their current shapes.
     std::vector<TuneKey> done;
-    for (const BatchGroup &grp : batch_groups(h_items, n_items)) {
-        const mtb_batch_item &f = h_items[grp.first];
-        const TuneKey key = tune_key(2 * (int)grp.items.size(), f.width, f.height, f.levels, f.row_stride);
+    std::vector<BatchUnit> u;
+    pair_units(h_items, n_items, &u);  // valid: the call above checked every item
+    for (const BatchGroup &grp : batch_groups(u)) {
+        const BatchUnit &f = u[grp.first];
+        const TuneKey key = tune_key(grp.images, f.W, f.H, f.L, f.stride);
         if (std::find(done.begin(), done.end(), key) != done.end())
             continue;
         done.push_back(key);
         Geometry g;
-        make_geometry(f.width, f.height, f.levels, &g);
+        make_geometry(f.W, f.H, f.L, &g);
         auto run = [&](const LaunchTune &t) {
             return align_batch(h_items, n_items, exclude_range, d_workspace, workspace_bytes, d_shifts, d_errs, s,
                                &key, &t);
         };
         LaunchTune best;
         float ms = 0.f, def = 0.f;
-        st = tune_one(g, (int)grp.items.size(), current_device_cus(), s, run, &best, &ms, &def);
+        st = tune_one(g, group_pairs(u, grp), current_device_cus(), s, run, &best, &ms, &def);
         if (st != MTB_OK)
             return st;
         tune_store(key, best);

@@ -320,3 +320,47 @@ def test_stream_probe_validation(mtb):
     assert L.mtb_probe_stream(A, 1 << 20, None, 4096, None) == 1          # writes without a destination
     assert L.mtb_probe_stream(ctypes.c_void_p(0x10004), 1 << 20, B, 0, None) == 1  # misaligned
     assert L.mtb_probe_stream(A, 1 << 20, B, 1 << 18, None) == 4          # valid, but no device here
+
+
+def _stacks(mtb, specs):
+    """Stack items with fake device pointers: specs [(n, w, h, L, stride, ref_index)]."""
+    from paper_2007_06483_amd import _BatchStack
+
+    arr = (_BatchStack * len(specs))()
+    keep = []
+    for i, (n, w, h, L, stride, ref) in enumerate(specs):
+        ptrs = (ctypes.c_void_p * n)(*[0x1000 + 0x10000 * i + 0x100 * k for k in range(n)])
+        keep.append(ptrs)
+        arr[i] = _BatchStack(ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), n, ref, stride, w, h, L, 0)
+    return arr, keep
+
+
+def test_stack_batch_workspace_and_validation(mtb):
+    L = _c(mtb)
+    items, keep = _stacks(mtb, [(3, 64, 48, 3, 192, -1), (5, 32, 24, 2, 96, 0), (1, 64, 48, 3, 192, -1)])
+    ws = L.mtb_batch_stacks_workspace_bytes(items, 3)
+    assert ws > 0
+    # A stack batch of pairs needs what the pair batch of the same pairs needs.
+    two, keep2 = _stacks(mtb, [(2, 64, 48, 3, 192, 0), (2, 32, 24, 2, 96, 0)])
+    pairs = _items(mtb, [(64, 48, 3, 192), (32, 24, 2, 96)])
+    assert L.mtb_batch_stacks_workspace_bytes(two, 2) == L.mtb_batch_workspace_bytes(pairs, 2)
+    assert L.mtb_batch_stacks_workspace_bytes(None, 3) == 0
+    assert L.mtb_batch_stacks_workspace_bytes(items, 0) == 0
+    args = [items, 3, 4, FAKE, ws, FAKE, FAKE, NULL]
+    for i, v in ((0, NULL), (1, 0), (1, 4097), (2, -1), (2, 256), (3, NULL), (5, NULL), (6, NULL)):
+        bad = list(args)
+        bad[i] = v
+        assert L.mtb_align_batch_stacks(*bad) == 1, (i, v)
+    bad = list(args)
+    bad[4] = ws - 1
+    assert L.mtb_align_batch_stacks(*bad) == 2
+    for field, value in (("n", 0), ("n", 33), ("ref_index", 5), ("ref_index", -2), ("levels", 7),
+                         ("row_stride", 95), ("reserved", 1), ("d_rgb", None), ("width", 0)):
+        broken, keep3 = _stacks(mtb, [(3, 64, 48, 3, 192, -1), (5, 32, 24, 2, 96, 0)])
+        setattr(broken[1], field, value)
+        assert L.mtb_batch_stacks_workspace_bytes(broken, 2) == 0, field
+        assert L.mtb_align_batch_stacks(broken, 2, 4, FAKE, ws, FAKE, FAKE, NULL) == 1, field
+    # A null image pointer inside a stack is refused too.
+    holes, keep4 = _stacks(mtb, [(3, 64, 48, 3, 192, -1)])
+    keep4[0][1] = None
+    assert L.mtb_batch_stacks_workspace_bytes(holes, 1) == 0

@@ -141,3 +141,51 @@ def test_batch64_uneven_full_size(mtb):
     for k, (shift, err) in enumerate(want):
         assert tuple(shifts[k]) == shift, k
         assert errs[k] == err, k
+
+
+# ---------------------------------------------------------------- stacks as items
+
+
+def _stack_specs():
+    # (images, width, height, levels, reference or None for n // 2, extra row pixels): uneven
+    # sizes, several stacks of one size sharing a launch set, single-image and two-image
+    # stacks, a reference away from the middle, padded rows, and nine 4-image stacks of one
+    # size (36 images: more than one launch set holds).
+    specs = [(3, 640, 480, 5, None, 0), (5, 400, 300, 4, 0, 0), (2, 640, 480, 5, 1, 0), (1, 200, 150, 3, None, 0),
+             (4, 900, 600, 6, None, 5), (3, 640, 480, 5, 2, 0)]
+    specs += [(4, 320, 240, 4, None, 0)] * 9
+    return specs
+
+
+def test_stack_batch_matches_oracle_and_single_stacks(mtb):
+    stacks, dev = [], []
+    for k, (n, w, h, L, ref, extra) in enumerate(_stack_specs()):
+        imgs, _, _ = synth.make_stack(w, h, n, max(8, w * h // 6000), 700 + k, min(w, h) // 8, sat_frac=0.05)
+        stacks.append((imgs, L, ref))
+        dev.append(([_to_dev(im, extra) for im in imgs], L, ref))
+    got = mtb.mtb_align_batch_stacks(dev)
+    torch.cuda.synchronize()
+    g_sh, g_er = got["shifts"].cpu().numpy(), got["errs"].cpu().numpy().astype(np.int64)
+    assert got["starts"][1] == 3 and len(g_sh) == sum(s[0] for s in _stack_specs())
+    for (imgs, L, ref), (d, _, _), r0 in zip(stacks, dev, got["starts"]):
+        n = len(imgs)
+        want = oracle.align_stack(imgs, L, ref_index=ref, threads=4)
+        assert np.array_equal(g_sh[r0:r0 + n], want["shifts"]), (n, L, ref)
+        assert np.array_equal(g_er[r0:r0 + n], want["errs"]), (n, L, ref)
+        alone = mtb.mtb_align_stack(d, L, ref_index=-1 if ref is None else ref)
+        torch.cuda.synchronize()
+        assert np.array_equal(alone["shifts"].cpu().numpy(), g_sh[r0:r0 + n])
+
+
+def test_stack_batch_of_pairs_equals_pair_batch(mtb):
+    # Two-image stacks with the reference first are the pair batch's items.
+    items = _rect_items([(640, 480, 5), (321, 243, 5), (640, 480, 5)], 930)
+    pairs = [(_to_dev(r), _to_dev(m), L) for r, m, L in items]
+    by_pairs = mtb.mtb_align_batch(pairs)
+    by_stacks = mtb.mtb_align_batch_stacks([([r, m], L, 0) for r, m, L in pairs])
+    torch.cuda.synchronize()
+    sh = by_stacks["shifts"].cpu().numpy().reshape(3, 2, 2)
+    er = by_stacks["errs"].cpu().numpy().reshape(3, 2)
+    assert np.array_equal(sh[:, 0], np.zeros((3, 2), np.int32)) and np.array_equal(er[:, 0], np.zeros(3))
+    assert np.array_equal(sh[:, 1], by_pairs["shifts"].cpu().numpy())
+    assert np.array_equal(er[:, 1], by_pairs["errs"].cpu().numpy())
