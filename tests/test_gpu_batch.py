@@ -189,3 +189,40 @@ def test_stack_batch_of_pairs_equals_pair_batch(mtb):
     assert np.array_equal(sh[:, 0], np.zeros((3, 2), np.int32)) and np.array_equal(er[:, 0], np.zeros(3))
     assert np.array_equal(sh[:, 1], by_pairs["shifts"].cpu().numpy())
     assert np.array_equal(er[:, 1], by_pairs["errs"].cpu().numpy())
+
+
+def test_stack_batch_graph_replay(mtb):
+    # The stacked batch (its output clearing included) captured once and
+    # replayed: every replay reproduces the eager rows, with eager work of
+    # the program between replays.
+    dev = []
+    for k, (n, w, h, L) in enumerate([(3, 320, 240, 5), (2, 128, 96, 4), (4, 320, 240, 5), (1, 64, 48, 3)]):
+        imgs, _, _ = synth.make_stack(w, h, n, 12, 980 + k, min(w, h) // 8)
+        dev.append(([_to_dev(im) for im in imgs], L, None))
+    eager = mtb.mtb_align_batch_stacks(dev)
+    torch.cuda.synchronize()
+    ref_shifts, ref_errs = eager["shifts"].clone(), eager["errs"].clone()
+    ws = torch.empty_like(eager["workspace"])
+    shifts = torch.empty_like(ref_shifts)
+    errs = torch.empty_like(ref_errs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream
+        mtb.mtb_align_batch_stacks(dev, workspace=ws, shifts=shifts, errs=errs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mtb.mtb_align_batch_stacks(dev, workspace=ws, shifts=shifts, errs=errs)
+    other = _rect_items([(200, 100, 4)], 995)
+    other_dev = [(_to_dev(r), _to_dev(m), L) for r, m, L in other]
+    for rep in range(3):
+        shifts.fill_(-99)
+        errs.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(shifts, ref_shifts), f"replay {rep}"
+        assert torch.equal(errs, ref_errs), f"replay {rep}"
+        mtb.mtb_align_batch(other_dev)
+        torch.cuda.synchronize()
