@@ -271,8 +271,7 @@ mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int
  *   - the search: how many of the coarsest levels are searched over
  *     exhaustive windows (radius 1, 3, 7, 15, 31 from the coarsest down;
  *     -1: the built-in rule, up to three levels of at most 8192 words of
- *     32 bits, and a fourth and fifth while the launch's window cells times
- *     words stay within 2^25; 0..5; the results are the same either way),
+ *     32 bits; 0..5; the results are the same either way),
  *     and per fine level the rows each row stream covers
  *     and the lanes of a row stream (8, 16, 32 or 64; 0: the built-in rules,
  *     the fewest rows that keep one level's grid within one resident round

@@ -2171,30 +2171,21 @@ hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s, int block
     return launch_bitmaps_w<4>(a, cus, s, blocks_pct);
 }
 
-// The i-th coarsest level is searched exhaustively when i < kCoarseLevels and
-// its window rows stay cheap for one workgroup: at most kCoarseDwords dwords.
-// The windows of radius 15 and 31 (i = 3, 4) also have to keep the launch's
-// work (window cells x dwords, over all pairs) within kCoarseWork: a small
-// pair then searches every level in this one launch instead of a chain of
-// fine launches, while large images keep the nine-candidate search there.
+// The built-in rule searches the i-th coarsest level exhaustively when i < 3
+// and its window rows stay cheap for one workgroup: at most kCoarseDwords
+// dwords.  The windows of radius 15 and 31 (i = 3, 4) are taken only when a
+// launch shape asks for them: on a mix of small stacks they cost more than
+// the fine launches they replace, and pairs small enough to gain from them
+// are searched by one workgroup instead.
 constexpr int64_t kCoarseDwords = 8192;
-constexpr int64_t kCoarseWork = (int64_t)1 << 25;
+constexpr int kCoarseRule = 3;
 
 int coarse_level_count(const Geometry &g, int npairs)
 {
+    (void)npairs;
     int cn = 0;
-    int64_t work = 0;
-    while (cn < kCoarseLevels && cn < g.L) {
-        const LevelGeom &lv = g.lv[g.L - 1 - cn];
-        const int64_t dwords = (int64_t)2 * lv.wpr * lv.h;
-        if (dwords > kCoarseDwords)
-            break;
-        const int64_t side = 2 * coarse_radius(cn) + 1;
-        work += side * side * dwords * (npairs > 0 ? npairs : 1);
-        if (cn >= 3 && work > kCoarseWork)
-            break;
+    while (cn < kCoarseRule && cn < g.L && (int64_t)2 * g.lv[g.L - 1 - cn].wpr * g.lv[g.L - 1 - cn].h <= kCoarseDwords)
         ++cn;
-    }
     return cn;
 }
 
