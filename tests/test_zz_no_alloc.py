@@ -1,9 +1,9 @@
 """The allocation-free pair search (mtb_align_pair_scratch, search state in the
 library's static device array) against mtb_align_pair with a workspace, through
-the C ABI: two calls in a row on the same device, the second on a smaller pair
-with fewer levels, and every output (shift, error, the nine errors and the
-chosen shift of every level) must be identical; the first pair is also checked
-against the oracle."""
+the C ABI: calls in a row on the same device, each on a smaller pair with fewer
+levels than the one before, and every output (shift, error, the nine errors
+and the chosen shift of every level) must be identical; each pair is also
+checked against the oracle."""
 
 import numpy as np
 import pytest
@@ -36,7 +36,10 @@ def _bitmaps(mtb, img, L):
 
 
 def test_scratch_search_equals_workspace_search(mtb):
-    cases = [(1024, 768, 7, 50, 3), (300, 200, 4, 12, 7)]  # second call: smaller input, fewer levels
+    # Second call: a smaller input with fewer levels that still keeps its
+    # search state in the static array; third: a pair small enough for the
+    # one-workgroup search, which keeps none.
+    cases = [(1024, 768, 7, 50, 3), (640, 480, 5, 12, 7), (300, 200, 4, 12, 9)]
     for w, h, L, t, seed in cases:
         ref, mov, _ = synth.make_rect_pair(w, h, 24, seed, t)
         bref, bmov = _bitmaps(mtb, ref, L), _bitmaps(mtb, mov, L)
