@@ -120,7 +120,9 @@ size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32
  * buffer and bitmaps buffer (layouts as described at mtb_layout) inside a
  * workspace at d_workspace: h_pyramids[i] and h_bitmaps[i] receive device
  * addresses inside that workspace, for i < n.  Nothing is read or written on
- * the device.
+ * the device.  The alignment calls form level 1's bitmaps from level 0's
+ * gray and do not store level 1's gray (mtb_build_pyramid does); every other
+ * part of both layouts is filled in.
  * Errors: MTB_ERR_INVALID_ARG (null pointers, n, sizes or levels out of range).
  */
 mtb_status mtb_stack_image_buffers(const void *d_workspace, int32_t n, int32_t width, int32_t height,

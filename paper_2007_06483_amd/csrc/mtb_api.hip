@@ -129,12 +129,20 @@ int row_alignment(const uint8_t *p, int64_t stride)
     return v % 16 == 0 ? 16 : (v % 4 == 0 ? 4 : 1);
 }
 
-void fill_chunk_starts(const Geometry &g, int64_t *cs)
+// First chunk of each level within one image.  With `pairs`, level 0 counts
+// units of two rows by kPairWords words and level 1 none (its bitmaps come
+// from level 0's units).
+void fill_chunk_starts(const Geometry &g, int64_t *cs, bool pairs = false)
 {
     cs[0] = 0;
     for (int l = 0; l < g.L; ++l) {
         const int64_t words = (int64_t)g.lv[l].h * g.lv[l].wpr;
-        cs[l + 1] = cs[l] + (words + kChunkWords - 1) / kChunkWords;
+        int64_t chunks = (words + kChunkWords - 1) / kChunkWords;
+        if (pairs && l == 0)
+            chunks = (int64_t)((g.lv[0].h + 1) / 2) * ((g.lv[0].wpr + kPairWords - 1) / kPairWords);
+        else if (pairs && l == 1)
+            chunks = 0;
+        cs[l + 1] = cs[l] + chunks;
     }
 }
 
@@ -164,6 +172,9 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
 {
     const int n = ps.n, npairs = ps.npairs;
     const int64_t mb = bytemaps ? g.bytemaps_bytes : g.bitmaps_bytes;  // maps buffer per image
+    // The packed bitmaps take levels 0 and 1 from level 0's gray, so level
+    // 1's gray is not stored; the byte maps read every level's gray.
+    const bool pairs = !bytemaps && g.L >= 2;
     uint8_t *pyr0 = ws;
     uint8_t *bm0 = pyr0 + n * g.pyramid_bytes;
     uint32_t *state = (uint32_t *)(bm0 + n * mb);
@@ -188,6 +199,7 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     pa.stride = stride;
     pa.n = n;
     pa.align = align;
+    pa.skip_l1 = pairs;
     pa.g = g;
     e = launch_pyramid(pa, cus, s, t.pyr_pct, t.pyr_group_log2);
     if (e != hipSuccess)
@@ -201,8 +213,9 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
     }
     ba.n = n;
     ba.exclude = exclude;
+    ba.pairs = pairs;
     ba.g = g;
-    fill_chunk_starts(g, ba.chunk_start);
+    fill_chunk_starts(g, ba.chunk_start, pairs);
     e = bytemaps ? launch_bytemaps(ba, cus, s) : launch_bitmaps(ba, cus, s, t.bm_pct, t.bm_waves);
     if (e != hipSuccess || npairs == 0)
         return e;

@@ -79,7 +79,7 @@ struct PyramidArgs {
     int32_t align;           // 16, 4 or 1: alignment every RGB row start is known to have
     int32_t merge;           // 1: histograms merged through per-XCD copies (see k_pyramid)
     int32_t group_log2;      // a workgroup takes 2^group_log2 consecutive tiles of a row at a time
-    int32_t pad_;
+    int32_t skip_l1;         // 1: level 1's gray is not stored (the bitmaps pass forms it from level 0)
     Geometry g;
 };
 
@@ -95,13 +95,19 @@ struct CoarsePyramidArgs {
 // The bitmaps pass walks each level as a flat run of 64-pixel words, in
 // chunks of kChunkWords words (kChunkWords * 64 gray bytes) per wavefront.
 constexpr int kChunkWords = 32;
+// With `pairs` set, level 0 is walked instead in units of two rows by
+// kPairWords words, and each unit also yields the level-1 bitmaps below it
+// (level 1 then has no chunks of its own and its gray is not read).
+constexpr int kPairWords = 16;
 
 struct BitmapArgs {
     const uint8_t *pyr[kMaxStack];
     uint8_t *bm[kMaxStack];
     int32_t n;
     int32_t exclude;
-    int64_t chunk_start[kMaxLevels + 1];  // first chunk of each level within one image
+    int32_t pairs;   // 1: levels 0 and 1 from level 0's gray, in two-row units
+    int32_t pad_;
+    int64_t chunk_start[kMaxLevels + 1];  // first chunk (or unit) of each level within one image
     Geometry g;
 };
 

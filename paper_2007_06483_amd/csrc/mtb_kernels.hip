@@ -434,8 +434,9 @@ __global__ __launch_bounds__(256) void k_pyramid(PyramidArgs a)
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 if (y1 + i < l1.h && x1 < l1.w) {
-                    *(uint2 *)(pyr + l1.gray_off + (int64_t)(y1 + i) * l1.gray_pitch + x1) =
-                        make_uint2(pack4(&u1[i][0]), pack4(&u1[i][4]));
+                    if (!a.skip_l1)
+                        *(uint2 *)(pyr + l1.gray_off + (int64_t)(y1 + i) * l1.gray_pitch + x1) =
+                            make_uint2(pack4(&u1[i][0]), pack4(&u1[i][4]));
 #pragma unroll
                     for (int j = 0; j < 8; ++j)
                         if (x1 + j < l1.w)
@@ -566,7 +567,7 @@ __device__ uint32_t wave_median(const uint32_t *hist, uint32_t npix)
         else if ((c += h.z) >= need)
             v = 4 * lane + 2;
     }
-    return __shfl(v, f < 0 ? 0 : f);
+    return __builtin_amdgcn_readfirstlane(__shfl(v, f < 0 ? 0 : f));
 }
 
 
@@ -574,12 +575,14 @@ struct ChunkPos {
     int img, level, w0, cnt;
 };
 
-__device__ __forceinline__ ChunkPos chunk_pos(const BitmapArgs &a, int64_t c, int64_t per_image)
+// Chunk c of a walk over levels l0 .. L-1 of every image (per_image chunks
+// each).
+__device__ __forceinline__ ChunkPos chunk_pos(const BitmapArgs &a, int64_t c, int64_t per_image, int l0)
 {
     ChunkPos p;
     p.img = (int)(c / per_image);
-    const int64_t cc = c - (int64_t)p.img * per_image;
-    int l = 0;
+    const int64_t cc = c - (int64_t)p.img * per_image + a.chunk_start[l0];
+    int l = l0;
     while (cc >= a.chunk_start[l + 1])
         ++l;
     p.level = l;
@@ -589,9 +592,9 @@ __device__ __forceinline__ ChunkPos chunk_pos(const BitmapArgs &a, int64_t c, in
     return p;
 }
 
-// The chunk after p, and col0 = p.w0 mod wpr of its level, without divisions
-// (every level holds at least one word).
-__device__ __forceinline__ void next_chunk(const BitmapArgs &a, ChunkPos &p, int &col0)
+// The chunk after p in a walk over levels l0 .. L-1, and col0 = p.w0 mod wpr
+// of its level, without divisions (every level holds at least one word).
+__device__ __forceinline__ void next_chunk(const BitmapArgs &a, ChunkPos &p, int &col0, int l0)
 {
     const LevelGeom *lv = &a.g.lv[p.level];
     p.w0 += kChunkWords;
@@ -600,7 +603,7 @@ __device__ __forceinline__ void next_chunk(const BitmapArgs &a, ChunkPos &p, int
         p.w0 = 0;
         col0 = 0;
         if (++p.level == a.g.L) {
-            p.level = 0;
+            p.level = l0;
             ++p.img;
         }
         lv = &a.g.lv[p.level];
@@ -711,28 +714,18 @@ __device__ __forceinline__ void te_bits(const uint32_t (&t)[8], const Thresholds
 // bits in registers: four pixels per dword compared at once (ByteGe), after a
 // byte transpose that lets the per-byte answers be gathered into bit order
 // with one shift and one and-or per dword.  Lane i then stores dword i of the
-// chunk's T words and of its E words.
-template <int kW>
-__global__ __launch_bounds__(64 * kW) void k_bitmaps(BitmapArgs a)
+// chunk's T words and of its E words.  This walks chunks c0 .. c1 - 1 of
+// levels l0 .. L-1 of every image (per_image chunks each).
+__device__ __forceinline__ void walk_chunks(const BitmapArgs &a, int64_t c0, int64_t c1, int64_t per_image, int l0,
+                                            int lane)
 {
-    const int wave = wave_id();
-    const int lane = threadIdx.x & 63;
     const Geometry &g = a.g;
-    const int64_t per_image = a.chunk_start[g.L];
-    const int64_t total = per_image * a.n;
-    const int64_t nwaves = (int64_t)gridDim.x * kW;
-    const int64_t gw = (int64_t)blockIdx.x * kW + wave;
-    const int64_t per_wave = (total + nwaves - 1) / nwaves;
-    const int64_t c0 = gw * per_wave;
-    const int64_t c1 = c0 + per_wave < total ? c0 + per_wave : total;
-    if (c0 >= c1)
-        return;
     const uint32_t X = (uint32_t)a.exclude;
 
     int cur_img = -1, cur_l = -1;
     uint32_t m = 0;
     Thresholds th = thresholds(0u, X);
-    ChunkPos p = chunk_pos(a, c0, per_image);
+    ChunkPos p = chunk_pos(a, c0, per_image, l0);
     int col0 = p.w0 % g.lv[p.level].wpr;
     uint4 v0, v1;
     load_chunk(a, p, lane, v0, v1);
@@ -753,7 +746,7 @@ __global__ __launch_bounds__(64 * kW) void k_bitmaps(BitmapArgs a)
 
         const uint32_t d[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
         if (c + 1 < c1) {
-            next_chunk(a, p, col0);
+            next_chunk(a, p, col0, l0);
             load_chunk(a, p, lane, v0, v1);
         }
         uint32_t t[8];
@@ -781,6 +774,199 @@ __global__ __launch_bounds__(64 * kW) void k_bitmaps(BitmapArgs a)
     }
 }
 
+// T and E answers of four pixels (byte b = pixel b) in bit 7 of each byte,
+// the case of te_bits picked at run time.
+__device__ __forceinline__ void te4(uint32_t x, const Thresholds &c, uint32_t &rt, uint32_t &re)
+{
+    const uint32_t xh = x | 0x80808080u;
+    const uint32_t dt = xh - c.low_t, dhi = xh - c.low_hi, dlo = xh - c.low_lo;
+    const uint32_t sl = c.nlow >= 1 ? ~0u : 0u, st = c.nlow >= 2 ? ~0u : 0u, sh = c.nlow >= 3 ? ~0u : 0u;
+    const uint32_t glo = (x & dlo) | (sl & (x | dlo));
+    const uint32_t gt = (x & dt) | (st & (x | dt));
+    const uint32_t ghi = (x & dhi) | (sh & (x | dhi));
+    rt = gt & c.keep_t;
+    re = (ghi & c.keep_hi) | ~glo;
+}
+
+// Bit 7 of byte b moved to bit b: after the shift the bytes' bits sit at 8b,
+// and the product takes bit 8b to 24 + b (0x01020408 = 2^24 + 2^17 + 2^10 +
+// 2^3); every other partial product lands below bit 24 or above bit 31, each
+// on a bit of its own, so nothing carries into bits 24..27.
+__device__ __forceinline__ uint32_t bits4(uint32_t r)
+{
+    return (((r >> 7) & 0x01010101u) * 0x01020408u) >> 24;
+}
+
+// The 8 level-1 pixels below a lane's 2 x 16 level-0 pixels of a pair unit
+// (d[0..3] row 2j, d[4..7] row 2j + 1, byte b of d[k] = pixel 4k + b): the
+// floor means of the 2x2 blocks, pixels 4h .. 4h + 3 in bytes 0..3 of g1[h].
+// Per dword pair: 16-bit sums of pixels (4k, 4k + 1) and (4k + 2, 4k + 3) of
+// both rows, then the floor of a quarter, in bytes 0 and 2.
+__device__ __forceinline__ void level1_gray(const uint32_t (&d)[8], uint32_t (&g1)[2])
+{
+    uint32_t q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t sum = (d[k] & 0x00ff00ffu) + ((d[k] >> 8) & 0x00ff00ffu) + (d[k + 4] & 0x00ff00ffu) +
+                             ((d[k + 4] >> 8) & 0x00ff00ffu);
+        q[k] = (sum >> 2) & 0x00ff00ffu;
+    }
+    g1[0] = __builtin_amdgcn_perm(q[1], q[0], 0x06040200u);
+    g1[1] = __builtin_amdgcn_perm(q[3], q[2], 0x06040200u);
+}
+
+// Segments of kPairWords words in a level-0 row.
+__device__ __forceinline__ int pair_segments(const Geometry &g) { return (g.lv[0].wpr + kPairWords - 1) / kPairWords; }
+
+// Lane `lane`'s gray bytes of pair unit (img, j, s): its 16 pixels of row 2j
+// (v0) and of row 2j + 1 (v1), columns 64 kPairWords s + 16 lane ..; zero
+// past the row's words and below the last row.
+__device__ __forceinline__ void load_unit(const BitmapArgs &a, int img, int j, int s, int lane, uint4 &v0, uint4 &v1)
+{
+    const LevelGeom &lv = a.g.lv[0];
+    const uint8_t *src = a.pyr[img] + lv.gray_off + (int64_t)(2 * j) * lv.gray_pitch + 64 * kPairWords * s + 16 * lane;
+    const bool in0 = kPairWords * s + (lane >> 2) < lv.wpr;
+    const bool in1 = in0 && 2 * j + 1 < lv.h;
+    v0 = in0 ? *(const uint4 *)src : make_uint4(0u, 0u, 0u, 0u);
+    v1 = in1 ? *(const uint4 *)(src + lv.gray_pitch) : make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Stores pair unit (img, j, s)'s level-0 T and E bits of the lane (tw, ew:
+// bits 0..15 its 16 pixels of row 2j, bits 16..31 those of row 2j + 1) and
+// the T and E bits of the 8 level-1 pixels g1 below them.  Lanes past a row's
+// words store no level-0 bits; their level-1 bits lie past level 1's width
+// and are stored as the row's zero padding.
+__device__ __forceinline__ void pair_unit(const BitmapArgs &a, int img, int j, int s, int lane,
+                                          const uint32_t (&g1)[2], uint32_t tw, uint32_t ew, const Thresholds &th1)
+{
+    const Geometry &g = a.g;
+    const LevelGeom &l0 = g.lv[0], &l1 = g.lv[1];
+    uint8_t *bm = a.bm[img];
+    const int x = 64 * kPairWords * s + 16 * lane;  // the lane's first level-0 column
+    const int nb = g.W - x;
+    const uint32_t keep = nb >= 16 ? 0xffffu : (nb <= 0 ? 0u : (1u << nb) - 1u);
+    const bool row1 = 2 * j + 1 < l0.h;
+    if (kPairWords * s + (lane >> 2) < l0.wpr) {
+        const int64_t o = (int64_t)(2 * j) * l0.wpr * 8 + x / 8;  // bytes into row 2j of a plane
+        *(uint16_t *)(bm + l0.tb_off + o) = (uint16_t)(tw & keep);
+        *(uint16_t *)(bm + l0.eb_off + o) = (uint16_t)(ew & keep);
+        if (row1) {
+            *(uint16_t *)(bm + l0.tb_off + o + 8 * l0.wpr) = (uint16_t)((tw >> 16) & keep);
+            *(uint16_t *)(bm + l0.eb_off + o + 8 * l0.wpr) = (uint16_t)((ew >> 16) & keep);
+        }
+    }
+    if (!row1)
+        return;  // level 1 has floor(h / 2) rows
+    uint32_t t8 = 0u, e8 = 0u;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint32_t rt, re;
+        te4(g1[h], th1, rt, re);
+        t8 |= bits4(rt) << (4 * h);
+        e8 |= bits4(re) << (4 * h);
+    }
+    const int x1 = x >> 1;
+    const int nb1 = l1.w - x1;
+    const uint32_t keep1 = nb1 >= 8 ? 0xffu : (nb1 <= 0 ? 0u : (1u << nb1) - 1u);
+    if ((x1 >> 6) < l1.wpr) {
+        const int64_t o1 = (int64_t)j * l1.wpr * 8 + (x1 >> 3);
+        bm[l1.tb_off + o1] = (uint8_t)(t8 & keep1);
+        bm[l1.eb_off + o1] = (uint8_t)(e8 & keep1);
+    }
+}
+
+// Walks pair units c0 .. c1 - 1 (a.chunk_start[1] per image, images one
+// after another).  Each unit is two level-0 rows by kPairWords words: lane i
+// takes 16 pixels of each row, the same 32-pixel transpose and compare as a
+// chunk give their level-0 T and E bits (row 2j in the low half), and the
+// 2x2 means of the same pixels give the 8 level-1 pixels below them, so that
+// level 1's gray is never read.
+__device__ __forceinline__ void walk_units(const BitmapArgs &a, int64_t c0, int64_t c1, int lane)
+{
+    const Geometry &g = a.g;
+    const uint32_t X = (uint32_t)a.exclude;
+    const int64_t units = a.chunk_start[1];
+    const int nseg = pair_segments(g);
+    int img = (int)(c0 / units);
+    int u = (int)(c0 - (int64_t)img * units);
+    int j = u / nseg, s = u - j * nseg;
+    int cur_img = -1;
+    uint32_t m0 = 0, m1 = 0;
+    Thresholds th0 = thresholds(0u, X), th1 = th0;
+    uint4 v0, v1;
+    load_unit(a, img, j, s, lane, v0, v1);
+    for (int64_t c = c0; c < c1; ++c) {
+        const int ci = img, cj = j, cs = s, cu = u;
+        if (ci != cur_img) {
+            const uint32_t *hist = (const uint32_t *)(a.pyr[ci] + g.hist_off);
+            m0 = wave_median(hist, (uint32_t)(g.lv[0].w * g.lv[0].h));
+            m1 = wave_median(hist + 256, (uint32_t)(g.lv[1].w * g.lv[1].h));
+            th0 = thresholds(m0, X);
+            th1 = thresholds(m1, X);
+            cur_img = ci;
+        }
+        if (cu == 0 && lane == 0) {
+            ((int32_t *)(a.bm[ci] + g.med_off))[0] = (int32_t)m0;
+            ((int32_t *)(a.bm[ci] + g.med_off))[1] = (int32_t)m1;
+        }
+        const uint32_t d[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        if (c + 1 < c1) {
+            ++u;
+            if (++s == nseg) {
+                s = 0;
+                ++j;
+            }
+            if (u == units) {
+                u = j = s = 0;
+                ++img;
+            }
+            load_unit(a, img, j, s, lane, v0, v1);
+        }
+        uint32_t g1[2];
+        level1_gray(d, g1);
+        uint32_t t[8];
+        transpose8(d, t);
+        uint32_t tw, ew;
+        switch (th0.nlow) {
+        case 0: te_bits<false, false, false>(t, th0, tw, ew); break;
+        case 1: te_bits<false, false, true>(t, th0, tw, ew); break;
+        case 2: te_bits<true, false, true>(t, th0, tw, ew); break;
+        default: te_bits<true, true, true>(t, th0, tw, ew); break;
+        }
+        pair_unit(a, ci, cj, cs, lane, g1, tw, ew, th1);
+    }
+}
+
+// The bitmaps pass.  Without kPairs every level is walked in chunks.  With
+// kPairs (a.pairs; at least two levels) the launch's items are first every
+// image's pair units, which yield levels 0 and 1, then every image's chunks
+// of levels 2 .. L-1; a wavefront takes a contiguous run of items.
+template <int kW, bool kPairs>
+__global__ __launch_bounds__(64 * kW) __attribute__((amdgpu_waves_per_eu(kPairs ? 6 : 1))) void k_bitmaps(BitmapArgs a)
+{
+    const int wave = wave_id();
+    const int lane = threadIdx.x & 63;
+    const int64_t per_image = a.chunk_start[a.g.L];
+    const int64_t total = per_image * a.n;
+    const int64_t nwaves = (int64_t)gridDim.x * kW;
+    const int64_t gw = (int64_t)blockIdx.x * kW + wave;
+    const int64_t per_wave = (total + nwaves - 1) / nwaves;
+    const int64_t c0 = gw * per_wave;
+    const int64_t c1 = c0 + per_wave < total ? c0 + per_wave : total;
+    if (c0 >= c1)
+        return;
+    if constexpr (!kPairs) {
+        walk_chunks(a, c0, c1, per_image, 0, lane);
+    } else {
+        const int64_t units = a.chunk_start[1];
+        const int64_t nu = units * a.n;
+        if (c0 < nu)
+            walk_units(a, c0, c1 < nu ? c1 : nu, lane);
+        if (c1 > nu)
+            walk_chunks(a, (c0 > nu ? c0 : nu) - nu, c1 - nu, per_image - units, 2, lane);
+    }
+}
+
 // The paper's representation, for comparison: T and E as one byte per pixel
 // (255 or 0), rows of gray_pitch bytes, padding bytes 0.  Same chunk walk as
 // k_bitmaps; lane i turns bytes [32 i, 32 i + 32) of a chunk into 32 T bytes
@@ -804,7 +990,7 @@ __global__ __launch_bounds__(256) void k_bytemaps(BitmapArgs a)
     uint32_t m = 0;
     ByteGe ge_t = byte_ge(0), ge_hi = byte_ge(0), ge_lo = byte_ge(0);
     uint32_t keep_t = 0, keep_hi = 0;
-    ChunkPos p = chunk_pos(a, c0, per_image);
+    ChunkPos p = chunk_pos(a, c0, per_image, 0);
     uint4 v0, v1;
     load_chunk(a, p, lane, v0, v1);
     for (int64_t c = c0; c < c1; ++c) {
@@ -825,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_bytemaps(BitmapArgs a)
             ((int32_t *)(a.bm[cp.img] + g.bmed_off))[cp.level] = (int32_t)m;
         const uint32_t d[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
         if (c + 1 < c1) {
-            p = chunk_pos(a, c + 1, per_image);
+            p = chunk_pos(a, c + 1, per_image, 0);
             load_chunk(a, p, lane, v0, v1);
         }
         // Valid bytes of the lane's 32 (columns below the level width).
@@ -2150,25 +2336,32 @@ hipError_t launch_search_bytes(SearchArgs a, int cus, hipStream_t s)
     return hipSuccess;
 }
 
-template <int kW>
+template <int kW, bool kPairs>
 hipError_t launch_bitmaps_w(const BitmapArgs &a, int cus, hipStream_t s, int blocks_pct)
 {
     const int64_t total = a.chunk_start[a.g.L] * a.n;
     int64_t blocks = (total + kW - 1) / kW;
-    const int64_t cap = (int64_t)cus * resident_per_cu<k_bitmaps<kW>, 64 * kW>() * blocks_pct / 100;
+    const int64_t cap = (int64_t)cus * resident_per_cu<k_bitmaps<kW, kPairs>, 64 * kW>() * blocks_pct / 100;
     blocks = blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
-    return launch_kernel("k_bitmaps", k_bitmaps<kW>, dim3((unsigned)blocks), dim3(64 * kW), s, a);
+    return launch_kernel("k_bitmaps", k_bitmaps<kW, kPairs>, dim3((unsigned)blocks), dim3(64 * kW), s, a);
+}
+
+template <bool kPairs>
+hipError_t launch_bitmaps_p(const BitmapArgs &a, int cus, hipStream_t s, int blocks_pct, int waves)
+{
+    // Wavefronts walk their items independently; the workgroup size only
+    // changes how the launch is cut (a launch-shape knob).
+    if (waves == 2)
+        return launch_bitmaps_w<2, kPairs>(a, cus, s, blocks_pct);
+    if (waves == 8)
+        return launch_bitmaps_w<8, kPairs>(a, cus, s, blocks_pct);
+    return launch_bitmaps_w<4, kPairs>(a, cus, s, blocks_pct);
 }
 
 hipError_t launch_bitmaps(const BitmapArgs &a, int cus, hipStream_t s, int blocks_pct, int waves)
 {
-    // Wavefronts walk their chunks independently; the workgroup size only
-    // changes how the launch is cut (a launch-shape knob).
-    if (waves == 2)
-        return launch_bitmaps_w<2>(a, cus, s, blocks_pct);
-    if (waves == 8)
-        return launch_bitmaps_w<8>(a, cus, s, blocks_pct);
-    return launch_bitmaps_w<4>(a, cus, s, blocks_pct);
+    return a.pairs ? launch_bitmaps_p<true>(a, cus, s, blocks_pct, waves)
+                   : launch_bitmaps_p<false>(a, cus, s, blocks_pct, waves);
 }
 
 // The built-in rule searches the i-th coarsest level exhaustively when i < 3

@@ -30,12 +30,16 @@ def test_algorithmic_bytes_of_the_stack_workload():
     lay = mtb.mtb_get_layout(W, H, L)
     per = bench.algorithmic_bytes(lay, n, n - 1)
     gray = sum((W >> l) * (H >> l) for l in range(L))
+    l1 = (W >> 1) * (H >> 1)  # level 1's gray: neither written nor read by the stack path
     maps = sum(8 * (((W >> l) + 63) // 64) * (H >> l) for l in range(L))
-    assert per["k_pyramid"] == n * (3 * W * H + gray) == 727985237
-    assert per["k_bitmaps"] == n * (gray + 2 * maps)
+    assert per["k_pyramid"] == n * (3 * W * H + gray - l1) == 685985237
+    assert per["k_bitmaps"] == n * (gray - l1 + 2 * maps)
     assert per["search"] == (n - 1) * 4 * maps
     assert per["step"] == per["k_pyramid"] + per["k_bitmaps"] + per["search"]
-    assert bench.pyramid_bytes(W, H, L) * n == per["k_pyramid"]
+    # The staged method's yardstick: every gray level written once and read once.
+    assert per["step_model"] == per["step"] + 2 * n * l1 == 1104578170
+    assert bench.pyramid_bytes(W, H, L, level1=False) * n == per["k_pyramid"]
+    assert bench.pyramid_bytes(W, H, L) * n == per["k_pyramid"] + n * l1
 
 
 def test_stored_traffic_applies_only_to_its_own_workload(tmp_path, monkeypatch):
