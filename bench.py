@@ -52,13 +52,14 @@ def level_sizes(lay):
             for l in range(lay.levels)]
 
 
-def algorithmic_bytes(lay, n_images, n_pairs):
+def algorithmic_bytes(lay, n_images, n_pairs, level1_kept=False):
     """Bytes each kernel of one stack alignment must move, per launch.
 
-    k_pyramid: RGB read (3 B/px) + every gray level but level 1 written once.
-    k_bitmaps: every gray level but level 1 read once + T and E words written
-               (level 1's bitmaps come from level 0's gray, so level 1's gray
-               is neither written nor read).
+    k_pyramid: RGB read (3 B/px) + every gray level written once, level 1
+               only when level1_kept.
+    k_bitmaps: every gray level read once (level 1 likewise) + T and E words
+               written; without level1_kept level 1's bitmaps come from level
+               0's gray, so level 1's gray is neither written nor read.
     search:    per pair and level, the four bitmaps read once.
     "step" is their sum; "step_model" is the staged method's traffic, in which
     every gray level is written once and read once (the workload's yardstick).
@@ -66,7 +67,7 @@ def algorithmic_bytes(lay, n_images, n_pairs):
     W, H = lay.width, lay.height
     lv = level_sizes(lay)
     gray = sum(w * h for w, h, _ in lv)
-    l1 = lv[1][0] * lv[1][1] if len(lv) > 1 else 0
+    l1 = lv[1][0] * lv[1][1] if len(lv) > 1 and not level1_kept else 0
     maps = sum(8 * wpr * h for _, h, wpr in lv)  # one bitmap plane, all levels
     per = {
         "k_pyramid": n_images * (3 * W * H + gray - l1),
@@ -212,6 +213,23 @@ def cpu_model():
     return None
 
 
+def batch_pyramid_bytes(mtb, items):
+    """k_pyramid bytes of one batch of pairs, items (W, H, L, row_stride): per
+    group of equal geometry (at most 16 pairs, as the library groups them),
+    level 1's gray counted where that group's launch set stores it."""
+    groups = {}
+    for it in items:
+        groups[it] = groups.get(it, 0) + 1
+    total = 0
+    for (W, H, L, stride), cnt in groups.items():
+        while cnt > 0:
+            k = min(cnt, 16)
+            cnt -= k
+            kept = not mtb.mtb_level1_from_level0(2 * k, W, H, stride, L)
+            total += 2 * k * pyramid_bytes(W, H, L, level1=kept)
+    return total
+
+
 def pyramid_bytes(W, H, L, level1=True):
     """Algorithmic bytes of one image in k_pyramid: RGB read + every gray level
     written (level 1 only where the path stores it: mtb_build_pyramid does, the
@@ -311,7 +329,7 @@ def run_batch(args, mtb, synth, torch, np, dev, compact=False):
         batched()
     ms_graph = timed(graph.replay, args.steps, 1)
 
-    pyr_bytes = sum(pyramid_bytes(it["W"], it["H"], it["L"], level1=False) * 2 for it in plain)
+    pyr_bytes = batch_pyramid_bytes(mtb, [(it["W"], it["H"], it["L"], int(it["r"].stride(0))) for it in plain])
     achieved = pyr_bytes * args.steps / (total_ms / 1e3) / 1e9
     result = {
         "metric": METRIC,
@@ -449,7 +467,9 @@ def run_quadrants(args, mtb, synth, torch, np, dev):
     ms = (time.perf_counter() - t) * 1e3 / args.steps
     launches, total_ms = mtb.mtb_profile_end()["k_pyramid"]
     qw, qh = W // 2, H // 2
-    algo = 8 * pyramid_bytes(qw, qh, L, level1=False)  # one launch: the four quadrants of both images
+    # One launch: the four quadrants of both images.
+    kept = not mtb.mtb_level1_from_level0(8, qw, qh, int(d[0].stride(0)), L)
+    algo = 8 * pyramid_bytes(qw, qh, L, level1=kept)
     achieved = algo / (total_ms / launches / 1e3) / 1e9
     got = [{k: v.cpu().numpy() for k, v in o.items()} for o in out]
     result = {
@@ -790,7 +810,8 @@ def main():
     shape = None
     if args.shape and not bytemaps:
         full = {"pyramid_slots_pct": 100, "pyramid_tile_group": 1, "bitmaps_blocks_pct": 100, "bitmaps_waves": 4,
-                "coarse_levels": -1, "small_search": -1, "search_rows": [], "search_lanes": []}
+                "coarse_levels": -1, "small_search": -1, "level1_from_level0": -1, "search_rows": [],
+                "search_lanes": []}
         full.update(json.loads(args.shape))
         mtb.mtb_set_shape(n, W, H, int(d_imgs[0].stride(0)), L, full)
         shape = dict(mtb.mtb_tuned_shape(n, W, H, int(d_imgs[0].stride(0)), L), step_ms=0.0, default_ms=0.0)
@@ -840,7 +861,8 @@ def main():
     gpu_shifts = shifts.cpu().numpy()
     gpu_errs = errs.cpu().numpy().astype(np.int64)
 
-    algo = algorithmic_bytes(lay, n, n - 1)
+    algo = algorithmic_bytes(lay, n, n - 1,
+                             level1_kept=not mtb.mtb_level1_from_level0(n, W, H, int(d_imgs[0].stride(0)), L))
     launches, total_ms = prof[dominant]
     avg_s = total_ms / launches / 1e3
     achieved = algo[dominant] / avg_s / 1e9
@@ -928,13 +950,14 @@ def main():
         "e2e_incl_h2d": {"ms_per_step": round(e2e_ms, 3), "MPps": round(mp_total / (e2e_ms / 1e3), 1)},
         "launch_shape": {"tuned": False, "pyramid_slots_pct": 100, "pyramid_tile_group": 1,
                          "bitmaps_blocks_pct": 100, "bitmaps_waves": 4, "coarse_levels": "built-in rule",
-                         "small_search": "built-in rule", "search_rows": "built-in rule",
-                         "search_lanes": "built-in rule"}
+                         "small_search": "built-in rule", "level1_from_level0": "built-in rule",
+                         "search_rows": "built-in rule", "search_lanes": "built-in rule"}
         if shape is None else {
             "tuned": bool(args.tune), "pyramid_slots_pct": shape["pyramid_slots_pct"],
             "pyramid_tile_group": shape["pyramid_tile_group"], "bitmaps_blocks_pct": shape["bitmaps_blocks_pct"],
             "bitmaps_waves": shape["bitmaps_waves"], "coarse_levels": shape["coarse_levels"],
-            "small_search": shape["small_search"], "search_rows": shape["search_rows"][:L], "search_lanes": shape["search_lanes"][:L],
+            "small_search": shape["small_search"], "level1_from_level0": shape["level1_from_level0"],
+            "search_rows": shape["search_rows"][:L], "search_lanes": shape["search_lanes"][:L],
             "tuner_step_ms": round(shape["step_ms"], 4), "tuner_default_ms": round(shape["default_ms"], 4)},
     }
 

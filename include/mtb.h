@@ -120,13 +120,22 @@ size_t mtb_stack_workspace_bytes(int32_t n, int32_t width, int32_t height, int32
  * buffer and bitmaps buffer (layouts as described at mtb_layout) inside a
  * workspace at d_workspace: h_pyramids[i] and h_bitmaps[i] receive device
  * addresses inside that workspace, for i < n.  Nothing is read or written on
- * the device.  The alignment calls form level 1's bitmaps from level 0's
- * gray and do not store level 1's gray (mtb_build_pyramid does); every other
- * part of both layouts is filled in.
+ * the device.  Where mtb_level1_from_level0 says so, the alignment calls form
+ * level 1's bitmaps from level 0's gray and do not store level 1's gray
+ * (mtb_build_pyramid always does); every other part of both layouts is
+ * filled in.
  * Errors: MTB_ERR_INVALID_ARG (null pointers, n, sizes or levels out of range).
  */
 mtb_status mtb_stack_image_buffers(const void *d_workspace, int32_t n, int32_t width, int32_t height,
                                    int32_t levels, void **h_pyramids, void **h_bitmaps);
+
+/*
+ * Whether the alignment calls, for a launch set of n images of this size,
+ * form level 1's bitmaps from level 0's gray and leave level 1's gray out of
+ * the workspace (1) or store it (0), under the shape stored for that key
+ * (see mtb_launch_shape) or the built-in rule.  -1 for arguments out of range.
+ */
+int32_t mtb_level1_from_level0(int32_t n, int32_t width, int32_t height, int64_t row_stride, int32_t levels);
 
 /*
  * Gray pyramid and per-level histograms of one RGB image (Section III-A:
@@ -281,7 +290,14 @@ mtb_status mtb_align_stack_chained(const uint8_t *const *h_d_rgb, int32_t n, int
  *     bitmap pyramids fit 144 KiB (every plane of the bitmaps buffer, from
  *     the end of its leading 256-byte guard to the medians) is searched by one
  *     workgroup that holds both in LDS and runs every level in one launch
- *     (-1 or 1, the default) or by the launches above (0).
+ *     (-1 or 1, the default) or by the launches above (0); and whether the
+ *     bitmaps pass forms level 1's bitmaps from level 0's gray, two rows at a
+ *     time, so that the pyramid pass need not store level 1's gray (1), or
+ *     stores and reads level 1's gray like every other level (0); the
+ *     built-in rule (-1) takes the first for launch sets of at least 96 Mi
+ *     level-0 pixels (n * width * height), where the 2 x 25 % of a level's
+ *     traffic it saves outweighs the bitmaps pass's second median per
+ *     wavefront.  Results are identical either way.
  * Shapes are kept per key (n images, width, height, levels, and whether
  * row_stride is a multiple of 16, else of 4, else neither) in a process-wide
  * table guarded by a mutex.  A key without a shape of its own uses the shape
@@ -298,6 +314,7 @@ typedef struct mtb_launch_shape {
     int32_t bitmaps_waves;      /* 2, 4 or 8 (default 4) */
     int32_t coarse_levels;      /* -1 (rule), 0 .. 5 */
     int32_t small_search;       /* -1 or 1: one workgroup per pair where it fits, 0: never */
+    int32_t level1_from_level0; /* -1: rule (sets of >= 96 Mi level-0 pixels), 0: never, 1: always */
     int32_t search_rows[16];    /* per level: 0, or a multiple of 4 in 4 .. 64 */
     int32_t search_lanes[16];   /* per level: 0, 8, 16, 32 or 64 */
     float step_ms;              /* tuners: median time of one call with this shape */

@@ -51,6 +51,7 @@ __all__ = [
     "mtb_test_fail_launch",
     "mtb_test_last_pyramid",
     "mtb_stack_image_buffers",
+    "mtb_level1_from_level0",
     "mtb_quadrant_workspace_bytes",
     "mtb_align_quadrants",
     "MTB_FILL_ZERO",
@@ -128,13 +129,14 @@ class _LaunchShape(ctypes.Structure):
     _fields_ = [("pyramid_slots_pct", ctypes.c_int32), ("pyramid_tile_group", ctypes.c_int32),
                 ("bitmaps_blocks_pct", ctypes.c_int32), ("bitmaps_waves", ctypes.c_int32),
                 ("coarse_levels", ctypes.c_int32), ("small_search", ctypes.c_int32),
+                ("level1_from_level0", ctypes.c_int32),
                 ("search_rows", ctypes.c_int32 * MTB_MAX_LEVELS),
                 ("search_lanes", ctypes.c_int32 * MTB_MAX_LEVELS), ("step_ms", ctypes.c_float),
                 ("default_ms", ctypes.c_float)]
 
 
 _SHAPE_DEFAULTS = {"pyramid_slots_pct": 100, "pyramid_tile_group": 1, "bitmaps_blocks_pct": 100,
-                   "bitmaps_waves": 4, "coarse_levels": -1, "small_search": -1}
+                   "bitmaps_waves": 4, "coarse_levels": -1, "small_search": -1, "level1_from_level0": -1}
 
 
 def _shape_dict(c: _LaunchShape) -> dict:
@@ -149,7 +151,7 @@ def _shape_struct(d: dict) -> _LaunchShape:
     lanes = list(d.get("search_lanes", [])) + [0] * MTB_MAX_LEVELS
     v = {k: int(d.get(k, dv)) for k, dv in _SHAPE_DEFAULTS.items()}
     return _LaunchShape(v["pyramid_slots_pct"], v["pyramid_tile_group"], v["bitmaps_blocks_pct"],
-                        v["bitmaps_waves"], v["coarse_levels"], v["small_search"],
+                        v["bitmaps_waves"], v["coarse_levels"], v["small_search"], v["level1_from_level0"],
                         (ctypes.c_int32 * MTB_MAX_LEVELS)(*rows[:MTB_MAX_LEVELS]),
                         (ctypes.c_int32 * MTB_MAX_LEVELS)(*lanes[:MTB_MAX_LEVELS]), 0.0, 0.0)
 
@@ -240,6 +242,8 @@ def lib():
     L.mtb_test_last_pyramid.restype = ctypes.c_int
     L.mtb_stack_image_buffers.argtypes = [P, i32, i32, i32, i32, ctypes.POINTER(P), ctypes.POINTER(P)]
     L.mtb_stack_image_buffers.restype = ctypes.c_int
+    L.mtb_level1_from_level0.argtypes = [i32, i32, i32, i64, i32]
+    L.mtb_level1_from_level0.restype = i32
     L.mtb_stage_rgb.argtypes = [P, i64, i32, i32, P, i64, P]
     L.mtb_stage_rgb.restype = ctypes.c_int
     L.mtb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_BatchItem), i32]
@@ -532,6 +536,15 @@ def mtb_stack_image_buffers(workspace: torch.Tensor, n: int, width: int, height:
            lib().mtb_stack_image_buffers(_ptr(workspace), n, width, height, levels, pyr, bms))
     base = workspace.data_ptr()
     return [(int(pyr[i]) - base, int(bms[i]) - base) for i in range(n)]
+
+
+def mtb_level1_from_level0(n: int, width: int, height: int, row_stride: int, levels: int) -> bool:
+    """Whether the alignment calls for n images of this size form level 1's bitmaps
+    from level 0's gray (and leave level 1's gray out of the workspace)."""
+    r = lib().mtb_level1_from_level0(n, width, height, row_stride, levels)
+    if r < 0:
+        raise MTBError("mtb_level1_from_level0", 1)  # MTB_ERR_INVALID_ARG
+    return bool(r)
 
 
 def mtb_apply_shifts(images, shifts: torch.Tensor, fill: int = MTB_FILL_ZERO, out=None,

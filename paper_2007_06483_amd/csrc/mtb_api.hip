@@ -164,6 +164,24 @@ int64_t set_workspace_bytes(const Geometry &g, int n, int npairs, bool bytemaps 
            npairs * state_stride_words(g.L) * 4 + align_up(4 * kTicketWords, kAlign);
 }
 
+// Launch sets of at least this many level-0 pixels (n * W * H) form level 1's
+// bitmaps from level 0's gray by default: below it the bitmaps pass's second
+// median per wavefront costs more than the level-1 traffic it saves
+// (measured: 2 x 6000x4000 +1.3 us, 4 x 4096x3072 +1.5 us, 3 x 6000x4000
+// even, 5 x 6000x4000 -2.5 us, 7 x 6000x4000 -8 to -11 us).
+constexpr int64_t kL1MinPixels = (int64_t)96 << 20;
+
+// Whether a launch set of n images takes level 1's bitmaps from level 0's
+// gray (and leaves level 1's gray unstored) under launch shape t.
+bool level1_from_level0(const Geometry &g, int n, const LaunchTune &t)
+{
+    if (g.L < 2)
+        return false;
+    if (t.l1 >= 0)
+        return t.l1 == 1;
+    return (int64_t)n * g.W * g.H >= kL1MinPixels;
+}
+
 // Enqueues a launch set on s.  `ws` is 256-byte aligned; `zero` lists output
 // regions to clear first (taken by value, its free slots are used here).
 hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int align, int exclude,
@@ -172,9 +190,9 @@ hipError_t enqueue_set(const PairSet &ps, const Geometry &g, int64_t stride, int
 {
     const int n = ps.n, npairs = ps.npairs;
     const int64_t mb = bytemaps ? g.bytemaps_bytes : g.bitmaps_bytes;  // maps buffer per image
-    // The packed bitmaps take levels 0 and 1 from level 0's gray, so level
-    // 1's gray is not stored; the byte maps read every level's gray.
-    const bool pairs = !bytemaps && g.L >= 2;
+    // The packed bitmaps may take levels 0 and 1 from level 0's gray, and
+    // level 1's gray is then not stored; the byte maps read every level's gray.
+    const bool pairs = !bytemaps && level1_from_level0(g, n, t);
     uint8_t *pyr0 = ws;
     uint8_t *bm0 = pyr0 + n * g.pyramid_bytes;
     uint32_t *state = (uint32_t *)(bm0 + n * mb);
@@ -311,6 +329,8 @@ bool shape_valid(const mtb_launch_shape &s)
         return false;
     if (s.small_search < -1 || s.small_search > 1)
         return false;
+    if (s.level1_from_level0 < -1 || s.level1_from_level0 > 1)
+        return false;
     for (int l = 0; l < kMaxLevels; ++l) {
         const int r = s.search_rows[l], w = s.search_lanes[l];
         if (r != 0 && (r < kRowsStep || r > kRowsMax || r % kRowsStep != 0))
@@ -330,6 +350,7 @@ LaunchTune from_shape(const mtb_launch_shape &s)
     t.bm_waves = s.bitmaps_waves;
     t.coarse = s.coarse_levels;
     t.small = s.small_search;
+    t.l1 = s.level1_from_level0;
     for (int l = 0; l < kMaxLevels; ++l) {
         t.rows[l] = s.search_rows[l];
         const int w = s.search_lanes[l];
@@ -347,6 +368,7 @@ void to_shape(const LaunchTune &t, mtb_launch_shape *s)
     s->bitmaps_waves = t.bm_waves;
     s->coarse_levels = t.coarse;
     s->small_search = t.small;
+    s->level1_from_level0 = t.l1;
     for (int l = 0; l < kMaxLevels; ++l) {
         s->search_rows[l] = t.rows[l];
         s->search_lanes[l] = t.cw[l] ? 1 << t.cw[l] : 0;
@@ -436,6 +458,13 @@ mtb_status tune_one(const Geometry &g, int npairs, int cus, hipStream_t s, Run r
     if (npairs > 0 && small_search_fits(g)) {
         LaunchTune c = best;
         c.small = 0;
+        consider(c);
+    }
+    for (int l1 : {0, 1}) {
+        if (g.L < 2)
+            break;
+        LaunchTune c = best;
+        c.l1 = l1;
         consider(c);
     }
     if (npairs > 0 && !small_search_used(g, &best)) {
@@ -994,6 +1023,16 @@ mtb_status mtb_stack_image_buffers(const void *d_workspace, int32_t n, int32_t w
     return MTB_OK;
 }
 
+int32_t mtb_level1_from_level0(int32_t n, int32_t width, int32_t height, int64_t row_stride, int32_t levels)
+{
+    Geometry g;
+    if (n < 1 || n > kMaxStack || row_stride < 3 * (int64_t)width || !make_geometry(width, height, levels, &g))
+        return -1;
+    LaunchTune t;
+    tune_lookup(tune_key(n, width, height, levels, row_stride), &t);
+    return level1_from_level0(g, n, t) ? 1 : 0;
+}
+
 mtb_status mtb_build_pyramid(const uint8_t *d_rgb, int32_t width, int32_t height,
                              int64_t row_stride, int32_t levels, void *d_pyramid,
                              size_t pyramid_bytes, void *stream)
@@ -1297,12 +1336,12 @@ mtb_status mtb_tune_save(const char *path)
     if (!f)
         return MTB_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
-    bool ok = fprintf(f, "mtb-tune 2 %s\n", platform.c_str()) > 0;
+    bool ok = fprintf(f, "mtb-tune 3 %s\n", platform.c_str()) > 0;
     for (const auto &kv : g_tune_table) {
         const TuneKey &k = kv.first;
         const LaunchTune &t = kv.second;
-        ok = ok && fprintf(f, "%d %d %d %d %d  %d %d %d %d %d %d ", k.n, k.w, k.h, k.levels, k.align, t.pyr_pct,
-                           t.pyr_group_log2, t.bm_pct, t.bm_waves, t.coarse, t.small) > 0;
+        ok = ok && fprintf(f, "%d %d %d %d %d  %d %d %d %d %d %d %d ", k.n, k.w, k.h, k.levels, k.align, t.pyr_pct,
+                           t.pyr_group_log2, t.bm_pct, t.bm_waves, t.coarse, t.small, t.l1) > 0;
         for (int l = 0; l < kMaxLevels && ok; ++l)
             ok = fprintf(f, " %d", t.rows[l]) > 0;
         for (int l = 0; l < kMaxLevels && ok; ++l)
@@ -1328,14 +1367,14 @@ mtb_status mtb_tune_load(const char *path, int32_t *h_loaded)
     std::vector<std::pair<TuneKey, LaunchTune>> got;
     bool ok = fgets(line, sizeof(line), f) != nullptr;
     // Shapes tuned on another architecture or HIP runtime are skipped whole.
-    const bool same = ok && std::string(line) == "mtb-tune 2 " + platform + "\n";
+    const bool same = ok && std::string(line) == "mtb-tune 3 " + platform + "\n";
     while (ok && same && fgets(line, sizeof(line), f)) {
         TuneKey k;
         LaunchTune t;
         int used = 0;
         const char *p = line;
-        ok = sscanf(p, "%d %d %d %d %d %d %d %d %d %d %d%n", &k.n, &k.w, &k.h, &k.levels, &k.align, &t.pyr_pct,
-                    &t.pyr_group_log2, &t.bm_pct, &t.bm_waves, &t.coarse, &t.small, &used) == 11;
+        ok = sscanf(p, "%d %d %d %d %d %d %d %d %d %d %d %d%n", &k.n, &k.w, &k.h, &k.levels, &k.align, &t.pyr_pct,
+                    &t.pyr_group_log2, &t.bm_pct, &t.bm_waves, &t.coarse, &t.small, &t.l1, &used) == 12;
         p += used;
         for (int l = 0; l < 2 * kMaxLevels && ok; ++l) {
             ok = sscanf(p, "%d%n", l < kMaxLevels ? &t.rows[l] : &t.cw[l - kMaxLevels], &used) == 1;

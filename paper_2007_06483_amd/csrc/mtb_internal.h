@@ -225,6 +225,7 @@ struct LaunchTune {
     int32_t bm_waves = 4;
     int32_t coarse = -1;
     int32_t small = -1;   // one-workgroup search where a pair fits LDS: -1 or 1 yes, 0 never
+    int32_t l1 = -1;      // level 1's bitmaps from level 0's gray: -1 rule, 0 never, 1 always
     int32_t rows[kMaxLevels] = {};
     int32_t cw[kMaxLevels] = {};
 };

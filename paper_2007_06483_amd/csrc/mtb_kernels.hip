@@ -539,12 +539,18 @@ __global__ __launch_bounds__(256) void k_pyramid_coarse(CoarsePyramidArgs a)
 
 // ---------------------------------------------------------------- pass 2
 
-// Lower median of a 256-bin histogram holding npix pixels, computed by one
-// wavefront: smallest v whose cumulative count reaches ceil(npix / 2).
-__device__ uint32_t wave_median(const uint32_t *hist, uint32_t npix)
+// A 256-bin histogram as one wavefront holds it: bins 4i .. 4i + 3 in lane i.
+__device__ __forceinline__ uint4 wave_hist(const uint32_t *hist)
+{
+    return *(const uint4 *)(hist + 4 * (threadIdx.x & 63));
+}
+
+// Lower median of a 256-bin histogram (as wave_hist loads it) holding npix
+// pixels, computed by one wavefront: smallest v whose cumulative count
+// reaches ceil(npix / 2).
+__device__ uint32_t wave_median_of(const uint4 h, uint32_t npix)
 {
     const int lane = threadIdx.x & 63;
-    const uint4 h = *(const uint4 *)(hist + 4 * lane);
     const uint32_t s = h.x + h.y + h.z + h.w;
     uint32_t incl = s;
 #pragma unroll
@@ -568,6 +574,11 @@ __device__ uint32_t wave_median(const uint32_t *hist, uint32_t npix)
             v = 4 * lane + 2;
     }
     return __builtin_amdgcn_readfirstlane(__shfl(v, f < 0 ? 0 : f));
+}
+
+__device__ __forceinline__ uint32_t wave_median(const uint32_t *hist, uint32_t npix)
+{
+    return wave_median_of(wave_hist(hist), npix);
 }
 
 
@@ -898,9 +909,11 @@ __device__ __forceinline__ void walk_units(const BitmapArgs &a, int64_t c0, int6
     for (int64_t c = c0; c < c1; ++c) {
         const int ci = img, cj = j, cs = s, cu = u;
         if (ci != cur_img) {
+            // Both histograms' loads are issued before either scan.
             const uint32_t *hist = (const uint32_t *)(a.pyr[ci] + g.hist_off);
-            m0 = wave_median(hist, (uint32_t)(g.lv[0].w * g.lv[0].h));
-            m1 = wave_median(hist + 256, (uint32_t)(g.lv[1].w * g.lv[1].h));
+            const uint4 h0 = wave_hist(hist), h1 = wave_hist(hist + 256);
+            m0 = wave_median_of(h0, (uint32_t)(g.lv[0].w * g.lv[0].h));
+            m1 = wave_median_of(h1, (uint32_t)(g.lv[1].w * g.lv[1].h));
             th0 = thresholds(m0, X);
             th1 = thresholds(m1, X);
             cur_img = ci;

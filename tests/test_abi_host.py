@@ -364,3 +364,22 @@ def test_stack_batch_workspace_and_validation(mtb):
     holes, keep4 = _stacks(mtb, [(3, 64, 48, 3, 192, -1)])
     keep4[0][1] = None
     assert L.mtb_batch_stacks_workspace_bytes(holes, 1) == 0
+
+
+def test_level1_from_level0_rule_and_shape(mtb):
+    # The built-in rule forms level 1's bitmaps from level 0's gray for launch
+    # sets of at least 96 Mi level-0 pixels; a stored shape overrides it.
+    mtb.mtb_tune_reset()
+    assert mtb.mtb_level1_from_level0(7, 6000, 4000, 18000, 7)          # 168 MP
+    assert mtb.mtb_level1_from_level0(8, 4096, 3072, 12288, 6)          # exactly 96 Mi
+    assert not mtb.mtb_level1_from_level0(3, 6000, 4000, 18000, 7)      # 72 MP
+    assert not mtb.mtb_level1_from_level0(2, 4096, 3072, 12288, 6)
+    assert not mtb.mtb_level1_from_level0(32, 6000, 4000, 18000, 1)     # one level: no level 1
+    mtb.mtb_set_shape(2, 640, 480, 1920, 5, {"level1_from_level0": 1})
+    assert mtb.mtb_level1_from_level0(2, 640, 480, 1920, 5)
+    mtb.mtb_set_shape(7, 6000, 4000, 18000, 7, {"level1_from_level0": 0})
+    assert not mtb.mtb_level1_from_level0(7, 6000, 4000, 18000, 7)
+    mtb.mtb_tune_reset()
+    for bad in [(0, 640, 480, 1920, 5), (33, 640, 480, 1920, 5), (2, 640, 480, 1000, 5), (2, 640, 480, 1920, 11)]:
+        with pytest.raises(RuntimeError):
+            mtb.mtb_level1_from_level0(*bad)

@@ -240,12 +240,12 @@ def test_stack_intermediates_match_oracle(mtb):
     lay = mtb.mtb_get_layout(321, 203, L)
     ws = got["workspace"]
     pyrs, bms = stack_workspace(mtb, ws, 3, lay)
+    # Below the size where the alignment calls form level 1's bitmaps from
+    # level 0's gray, level 1's gray is stored like every other level.
+    assert not mtb.mtb_level1_from_level0(3, 321, 203, 3 * 321, L)
     for i, p in enumerate(want["pyramids"]):
         for l, g in enumerate(gray_levels(pyrs[i], lay)):
-            # The stack path forms level 1's bitmaps from level 0's gray and
-            # does not store level 1's gray (mtb_build_pyramid does).
-            if l != 1:
-                assert np.array_equal(g, p.gray(l))
+            assert np.array_equal(g, p.gray(l))
         assert np.array_equal(histograms(pyrs[i], lay), p.hist)
         assert np.array_equal(medians(bms[i], lay), p.median)
         for l, (t, e, tp, ep) in enumerate(bitmaps(bms[i], lay)):
@@ -257,15 +257,22 @@ def test_stack_intermediates_match_oracle(mtb):
                                    (1024, 8, 4), (1025, 19, 5), (2049, 33, 6), (3000, 5, 2),
                                    (6000, 17, 3)])
 def test_stack_bitmaps_of_two_row_units(mtb, w, h, L):
-    # The stack path forms levels 0 and 1's bitmaps from level 0's gray in
-    # units of two rows by 1024 pixels: odd heights leave a last unit of one
-    # row (and no level-1 row), widths off a multiple of 1024 leave lanes past
-    # a row's words, and level 1's last padding word can lie past level 0's
-    # words.  Every bit, padding included, and every median must be the
-    # oracle's; shifts, errors and traces too.
+    # With level1_from_level0 (the built-in rule takes it for large launch
+    # sets; forced here) the bitmaps pass forms levels 0 and 1 from level 0's
+    # gray in units of two rows by 1024 pixels: odd heights leave a last unit
+    # of one row (and no level-1 row), widths off a multiple of 1024 leave
+    # lanes past a row's words, and level 1's last padding word can lie past
+    # level 0's words.  Every bit, padding included, and every median must be
+    # the oracle's; shifts, errors and traces too.
     imgs, _, _ = synth.make_stack(w, h, 2, max(2, w * h // 4000), 900 + w + h, min(3, w // 4, h // 4),
                                   sat_frac=0.05)
-    got, want = _check_stack(mtb, imgs, L)
+    mtb.mtb_tune_reset()
+    mtb.mtb_set_shape(2, w, h, 3 * w, L, {"level1_from_level0": 1})
+    assert mtb.mtb_level1_from_level0(2, w, h, 3 * w, L) == (L >= 2)
+    try:
+        got, want = _check_stack(mtb, imgs, L)
+    finally:
+        mtb.mtb_tune_reset()
     lay = mtb.mtb_get_layout(w, h, L)
     pyrs, bms = stack_workspace(mtb, got["workspace"], 2, lay)
     for i, p in enumerate(want["pyramids"]):
@@ -308,9 +315,8 @@ def test_repeated_runs_are_bit_identical(mtb):
     pa, ba = stack_workspace(mtb, a["workspace"], n, lay)
     pb, bb = stack_workspace(mtb, b["workspace"], n, lay)
     for i in range(n):
-        for l, (ga, gb) in enumerate(zip(gray_levels(pa[i], lay), gray_levels(pb[i], lay))):
-            if l != 1:  # not stored by the stack path
-                assert np.array_equal(ga, gb)
+        for ga, gb in zip(gray_levels(pa[i], lay), gray_levels(pb[i], lay)):
+            assert np.array_equal(ga, gb)
         assert np.array_equal(histograms(pa[i], lay), histograms(pb[i], lay))
         assert np.array_equal(medians(ba[i], lay), medians(bb[i], lay))
         for l in range(lay.levels):

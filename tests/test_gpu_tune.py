@@ -59,7 +59,7 @@ def test_tuned_shape_keeps_results_and_is_stored(mtb):
     stored = mtb.mtb_tuned_shape(5, 900, 640, 2700, L)
     assert stored is not None
     keys = ("pyramid_slots_pct", "pyramid_tile_group", "bitmaps_blocks_pct", "bitmaps_waves", "coarse_levels",
-            "small_search", "search_rows", "search_lanes")
+            "small_search", "level1_from_level0", "search_rows", "search_lanes")
     assert {k: stored[k] for k in keys} == {k: shape[k] for k in keys}
     after = _run(mtb, d, L)
     for a, b in zip(before, after):
@@ -93,13 +93,13 @@ def test_explicit_shapes_give_identical_results(mtb, pyr, grp, bm, waves, coarse
 def test_tuned_shapes_survive_save_and_load(mtb, tmp_path):
     mtb.mtb_tune_reset()
     mtb.mtb_set_shape(4, 1100, 700, 3300, 6, {"pyramid_slots_pct": 150, "pyramid_tile_group": 2,
-                                              "bitmaps_waves": 8, "coarse_levels": 2, "search_rows": [16] * 16,
-                                              "search_lanes": [32] * 16})
+                                              "bitmaps_waves": 8, "coarse_levels": 2, "level1_from_level0": 1,
+                                              "search_rows": [16] * 16, "search_lanes": [32] * 16})
     before = mtb.mtb_tuned_shape(4, 1100, 700, 3300, 6)
     path = str(tmp_path / "shapes.txt")
     mtb.mtb_tune_save(path)
     first = open(path).readline().split()
-    assert first[:2] == ["mtb-tune", "2"] and first[2].startswith("gfx950") and first[3].startswith("hip-")
+    assert first[:2] == ["mtb-tune", "3"] and first[2].startswith("gfx950") and first[3].startswith("hip-")
     mtb.mtb_tune_reset()
     assert mtb.mtb_tuned_shape(4, 1100, 700, 3300, 6) is None
     assert mtb.mtb_tune_load(path) == 1
@@ -107,7 +107,7 @@ def test_tuned_shapes_survive_save_and_load(mtb, tmp_path):
     # A file written on another platform is skipped whole.
     other = str(tmp_path / "other.txt")
     lines = open(path).read().splitlines()
-    open(other, "w").write("\n".join(["mtb-tune 2 gfx942 hip-1"] + lines[1:]) + "\n")
+    open(other, "w").write("\n".join(["mtb-tune 3 gfx942 hip-1"] + lines[1:]) + "\n")
     mtb.mtb_tune_reset()
     assert mtb.mtb_tune_load(other) == 0
     assert mtb.mtb_tuned_shape(4, 1100, 700, 3300, 6) is None

@@ -19,12 +19,12 @@ def test_set_lookup_and_reset():
     key = (7, 6000, 4000, 18000, 7)
     assert mtb.mtb_tuned_shape(*key) is None
     mtb.mtb_set_shape(*key, {"pyramid_slots_pct": 200, "pyramid_tile_group": 2, "bitmaps_blocks_pct": 75,
-                             "bitmaps_waves": 8, "coarse_levels": 2, "small_search": 0, "search_rows": [8, 0, 16],
-                             "search_lanes": [0, 16, 64]})
+                             "bitmaps_waves": 8, "coarse_levels": 2, "small_search": 0, "level1_from_level0": 0,
+                             "search_rows": [8, 0, 16], "search_lanes": [0, 16, 64]})
     got = mtb.mtb_tuned_shape(*key)
     assert got["pyramid_slots_pct"] == 200 and got["bitmaps_blocks_pct"] == 75
     assert got["pyramid_tile_group"] == 2 and got["bitmaps_waves"] == 8 and got["coarse_levels"] == 2
-    assert got["small_search"] == 0
+    assert got["small_search"] == 0 and got["level1_from_level0"] == 0
     assert got["search_rows"][:4] == [8, 0, 16, 0]
     assert got["search_lanes"][:4] == [0, 16, 64, 0]
     # The key distinguishes image count, size, levels and the row-stride class.
@@ -41,7 +41,7 @@ def test_set_lookup_and_reset():
     {"bitmaps_blocks_pct": 101}, {"search_rows": [2]}, {"search_rows": [6]}, {"search_rows": [68]},
     {"search_rows": [0, -4]}, {"pyramid_tile_group": 3}, {"pyramid_tile_group": 0}, {"bitmaps_waves": 1},
     {"bitmaps_waves": 16}, {"coarse_levels": -2}, {"coarse_levels": 6}, {"small_search": 2},
-    {"small_search": -2}, {"search_lanes": [4]},
+    {"small_search": -2}, {"level1_from_level0": 2}, {"level1_from_level0": -2}, {"search_lanes": [4]},
     {"search_lanes": [0, 128]}, {"search_lanes": [24]},
 ])
 def test_out_of_range_shapes_are_refused(bad):
