@@ -799,28 +799,34 @@ __device__ __forceinline__ void te4(uint32_t x, const Thresholds &c, uint32_t &r
     re = (ghi & c.keep_hi) | ~glo;
 }
 
-// Bit 7 of byte b moved to bit b: after the shift the bytes' bits sit at 8b,
-// and the product takes bit 8b to 24 + b (0x01020408 = 2^24 + 2^17 + 2^10 +
-// 2^3); every other partial product lands below bit 24 or above bit 31, each
-// on a bit of its own, so nothing carries into bits 24..27.
-__device__ __forceinline__ uint32_t bits4(uint32_t r)
+// Bit 7 of byte b of r0 moved to bit b and bit 7 of byte b of r1 to bit 4 + b.
+// After the shifts byte b holds r0's bit at 8b and r1's at 8b + 4; the
+// product takes them to 24 + b and 28 + b (0x01020408 = 2^24 + 2^17 + 2^10 +
+// 2^3), and every other partial product lands below bit 24 or above bit 31,
+// each on a bit of its own, so nothing carries into bits 24..31.
+__device__ __forceinline__ uint32_t bits8(uint32_t r0, uint32_t r1)
 {
-    return (((r >> 7) & 0x01010101u) * 0x01020408u) >> 24;
+    const uint32_t u = ((r0 >> 7) & 0x01010101u) | ((r1 >> 3) & 0x10101010u);
+    return (u * 0x01020408u) >> 24;
 }
 
 // The 8 level-1 pixels below a lane's 2 x 16 level-0 pixels of a pair unit
 // (d[0..3] row 2j, d[4..7] row 2j + 1, byte b of d[k] = pixel 4k + b): the
 // floor means of the 2x2 blocks, pixels 4h .. 4h + 3 in bytes 0..3 of g1[h].
 // Per dword pair: 16-bit sums of pixels (4k, 4k + 1) and (4k + 2, 4k + 3) of
-// both rows, then the floor of a quarter, in bytes 0 and 2.
+// both rows (bytes 1 and 3 moved down by a v_perm_b32 whose selector 0x0c
+// yields zero bytes), a quarter of each in byte 0 and byte 2 (sums are at
+// most 1020, so the shift leaves each in its own byte), then bytes 0 and 2
+// of two such dwords gathered by one more v_perm_b32.
 __device__ __forceinline__ void level1_gray(const uint32_t (&d)[8], uint32_t (&g1)[2])
 {
     uint32_t q[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint32_t sum = (d[k] & 0x00ff00ffu) + ((d[k] >> 8) & 0x00ff00ffu) + (d[k + 4] & 0x00ff00ffu) +
-                             ((d[k + 4] >> 8) & 0x00ff00ffu);
-        q[k] = (sum >> 2) & 0x00ff00ffu;
+        const uint32_t a = d[k], b = d[k + 4];
+        const uint32_t sum = (a & 0x00ff00ffu) + __builtin_amdgcn_perm(0u, a, 0x0c030c01u) + (b & 0x00ff00ffu) +
+                             __builtin_amdgcn_perm(0u, b, 0x0c030c01u);
+        q[k] = sum >> 2;
     }
     g1[0] = __builtin_amdgcn_perm(q[1], q[0], 0x06040200u);
     g1[1] = __builtin_amdgcn_perm(q[3], q[2], 0x06040200u);
@@ -830,16 +836,19 @@ __device__ __forceinline__ void level1_gray(const uint32_t (&d)[8], uint32_t (&g
 __device__ __forceinline__ int pair_segments(const Geometry &g) { return (g.lv[0].wpr + kPairWords - 1) / kPairWords; }
 
 // Lane `lane`'s gray bytes of pair unit (img, j, s): its 16 pixels of row 2j
-// (v0) and of row 2j + 1 (v1), columns 64 kPairWords s + 16 lane ..; zero
-// past the row's words and below the last row.
+// (v0) and of row 2j + 1 (v1), columns 64 kPairWords s + 16 lane ..  The
+// loads never branch: a lane past the row's words reads the row's last 16
+// bytes and a missing row 2j + 1 (odd height) reads row 2j again; pair_unit
+// stores nothing from either (no level-0 bits past the row, zero level-1
+// bits past level 1's width, no level-1 row without row 2j + 1).
 __device__ __forceinline__ void load_unit(const BitmapArgs &a, int img, int j, int s, int lane, uint4 &v0, uint4 &v1)
 {
     const LevelGeom &lv = a.g.lv[0];
-    const uint8_t *src = a.pyr[img] + lv.gray_off + (int64_t)(2 * j) * lv.gray_pitch + 64 * kPairWords * s + 16 * lane;
-    const bool in0 = kPairWords * s + (lane >> 2) < lv.wpr;
-    const bool in1 = in0 && 2 * j + 1 < lv.h;
-    v0 = in0 ? *(const uint4 *)src : make_uint4(0u, 0u, 0u, 0u);
-    v1 = in1 ? *(const uint4 *)(src + lv.gray_pitch) : make_uint4(0u, 0u, 0u, 0u);
+    const int col = 64 * kPairWords * s + 16 * lane;
+    const int colc = col < (int)lv.gray_pitch - 16 ? col : (int)lv.gray_pitch - 16;
+    const uint8_t *row = a.pyr[img] + lv.gray_off + (int64_t)(2 * j) * lv.gray_pitch;
+    v0 = *(const uint4 *)(row + colc);
+    v1 = *(const uint4 *)(row + (2 * j + 1 < lv.h ? lv.gray_pitch : 0) + colc);
 }
 
 // Stores pair unit (img, j, s)'s level-0 T and E bits of the lane (tw, ew:
@@ -868,21 +877,16 @@ __device__ __forceinline__ void pair_unit(const BitmapArgs &a, int img, int j, i
     }
     if (!row1)
         return;  // level 1 has floor(h / 2) rows
-    uint32_t t8 = 0u, e8 = 0u;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        uint32_t rt, re;
-        te4(g1[h], th1, rt, re);
-        t8 |= bits4(rt) << (4 * h);
-        e8 |= bits4(re) << (4 * h);
-    }
+    uint32_t rt0, re0, rt1, re1;
+    te4(g1[0], th1, rt0, re0);
+    te4(g1[1], th1, rt1, re1);
     const int x1 = x >> 1;
     const int nb1 = l1.w - x1;
     const uint32_t keep1 = nb1 >= 8 ? 0xffu : (nb1 <= 0 ? 0u : (1u << nb1) - 1u);
     if ((x1 >> 6) < l1.wpr) {
         const int64_t o1 = (int64_t)j * l1.wpr * 8 + (x1 >> 3);
-        bm[l1.tb_off + o1] = (uint8_t)(t8 & keep1);
-        bm[l1.eb_off + o1] = (uint8_t)(e8 & keep1);
+        bm[l1.tb_off + o1] = (uint8_t)(bits8(rt0, rt1) & keep1);
+        bm[l1.eb_off + o1] = (uint8_t)(bits8(re0, re1) & keep1);
     }
 }
 
