@@ -707,7 +707,9 @@ def run_served(args, mtb, synth, torch, np, dev, compact_seconds=0.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    # 200 steps of the 7 x 24 MP stack take about 50 ms: enough that the first
+    # launch's latency and the evented steps add well under 1 % to a step.
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stack7_6000x4000",
                     choices=["stack7_6000x4000", "stack7_6000x4000_chained", "stack7_6000x4000_bytemaps",
@@ -728,8 +730,9 @@ def main():
     ap.add_argument("--shape", default=None,
                     help="stack workloads: a launch shape (JSON object of mtb_launch_shape fields) "
                          "stored with mtb_set_shape before timing")
-    ap.add_argument("--event-every", type=int, default=4,
-                    help="time the dominant kernel with HIP events in every N-th timed step")
+    ap.add_argument("--event-every", type=int, default=0,
+                    help="time the dominant kernel with HIP events in every N-th timed step "
+                         "(default: max(4, steps // 10), about ten evented steps)")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum wall time of the CPU oracle sample")
@@ -747,6 +750,8 @@ def main():
               "(stacks are independent, so it would shard by stack: each GPU aligns whole stacks, "
               "with no exchange between GPUs).", file=sys.stderr)
         sys.exit(2)
+    if args.event_every == 0:
+        args.event_every = max(4, args.steps // 10)
     if args.steps < 1 or args.warmup < 0 or args.event_every < 1:
         ap.error("--steps and --event-every must be >= 1 and --warmup >= 0")
 
