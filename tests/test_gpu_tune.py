@@ -69,10 +69,11 @@ def test_tuned_shape_keeps_results_and_is_stored(mtb):
     assert np.array_equal(after[1].astype(np.int64), want["errs"])
 
 
-@pytest.mark.parametrize("pyr,grp,bm,waves,coarse", [(25, 1, 25, 2, -1), (50, 2, 100, 8, 0), (200, 4, 50, 4, 3),
-                                                    (400, 1, 100, 8, 1), (100, 4, 75, 2, 2), (100, 1, 100, 4, 4),
-                                                    (100, 2, 100, 4, 5)])
-def test_explicit_shapes_give_identical_results(mtb, pyr, grp, bm, waves, coarse):
+@pytest.mark.parametrize("pyr,grp,bm,waves,coarse,l1", [(25, 1, 25, 2, -1, 1), (50, 2, 100, 8, 0, 1),
+                                                       (200, 4, 50, 4, 3, 0), (400, 1, 100, 8, 1, 0),
+                                                       (100, 4, 75, 2, 2, 1), (100, 1, 100, 4, 4, 1),
+                                                       (100, 2, 100, 4, 5, -1)])
+def test_explicit_shapes_give_identical_results(mtb, pyr, grp, bm, waves, coarse, l1):
     imgs, d = _stack(4, 1100, 700, 62, 30)
     L = 6
     mtb.mtb_tune_reset()
@@ -82,11 +83,12 @@ def test_explicit_shapes_give_identical_results(mtb, pyr, grp, bm, waves, coarse
     for rows, lanes in ((4, 8), (8, 64), (28, 16), (64, 32), (12, 0)):
         mtb.mtb_set_shape(4, 1100, 700, 3300, L, {"pyramid_slots_pct": pyr, "pyramid_tile_group": grp,
                                                   "bitmaps_blocks_pct": bm, "bitmaps_waves": waves,
-                                                  "coarse_levels": coarse, "search_rows": [rows] * 16,
-                                                  "search_lanes": [lanes] * 16})
+                                                  "coarse_levels": coarse, "level1_from_level0": l1,
+                                                  "search_rows": [rows] * 16, "search_lanes": [lanes] * 16})
+        assert mtb.mtb_level1_from_level0(4, 1100, 700, 3300, L) == (l1 == 1)
         got = _run(mtb, d, L)
         for a, b in zip(ref, got):
-            assert np.array_equal(a, b), (pyr, grp, bm, waves, coarse, rows, lanes)
+            assert np.array_equal(a, b), (pyr, grp, bm, waves, coarse, l1, rows, lanes)
     mtb.mtb_tune_reset()
 
 
